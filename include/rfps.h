@@ -1,0 +1,196 @@
+/*
+ * rfps.h -- C ABI of the RadiusFPS-G sampling library (librfps.so) for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library computes exact farthest point sampling (FPS): the standard FPS
+ * loop of Algorithm 1 (Sec. 2.1) with the exactness contract of Sec. 3.1
+ * (a fixed start point, one precision throughout, and arg max returning the
+ * smallest original index among equal distances).  RadiusFPS (Sec. 3) makes
+ * it faster by indexing the cloud with spherical voxels and skipping voxels
+ * and points that provably cannot change (Sec. 3.4.2, Sec. 3.4.3); the result
+ * is the same sequence plain FPS returns.
+ *
+ * Distances.  Every distance the library keeps or reports is the FP32
+ * squared Euclidean distance ((dx*dx + dy*dy) + dz*dz), dx = fl(p_x - s_x),
+ * evaluated without fused multiply-add.  The update is strict: a point's
+ * distance changes only when the new value is smaller.
+ *
+ * Memory.  The caller owns all memory.  Pointers documented as "device" are
+ * device (HBM) pointers; "host" pointers are read before the call returns.
+ * The library never allocates device memory and keeps no state between
+ * calls: everything a call needs lives in the caller's workspace.  A stream
+ * argument is a hipStream_t passed as void* (NULL = the default stream); all
+ * device work of a call is enqueued on it, in order, and the call returns
+ * without waiting for the device unless it says otherwise.
+ *
+ * Errors.  Argument errors the host can see (sizes, ranges, NULL pointers,
+ * a workspace that is too small) are returned at once and nothing is
+ * enqueued.  Errors only the device can see (a non-finite coordinate, a
+ * cloud that does not fit the on-chip budget, an expired wait) are recorded
+ * in the workspace; the sampler then writes -1 to every output index and NaN
+ * to every output distance, and rfps_read_status() reports the error.
+ */
+#ifndef RFPS_H
+#define RFPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rfps_status {
+    RFPS_OK = 0,
+    RFPS_ERR_INVALID_ARG = 1, /* bad size, range or NULL pointer */
+    RFPS_ERR_NONFINITE = 2,   /* an input coordinate is NaN or infinite */
+    RFPS_ERR_WORKSPACE = 3,   /* workspace NULL, misaligned or too small */
+    RFPS_ERR_DEVICE = 4,      /* a HIP runtime call failed */
+    RFPS_ERR_UNSUPPORTED = 5, /* no usable gfx950 device, or a launch shape it cannot run */
+    RFPS_ERR_CAPACITY = 6,    /* the cloud's share per workgroup exceeds the on-chip budget */
+    RFPS_ERR_TIMEOUT = 7      /* a bounded wait inside a persistent kernel expired */
+} rfps_status;
+
+/* rfps_params.flags */
+#define RFPS_F_NO_PRUNE 0x01u      /* visit every tile each iteration (no voxel pruning) */
+#define RFPS_F_NO_POINT_SKIP 0x02u /* no coordinate-wise point skip (Sec. 3.4.3) */
+#define RFPS_F_TELEMETRY 0x04u     /* count tests, prunes, visits and updates */
+#define RFPS_F_TRACE 0x08u         /* time every iteration of workgroup 0 */
+
+typedef struct rfps_params {
+    /* Voxel bins per axis, n_vox of eq. voxel_size (Sec. 3.2); 1..1024.
+     * 0 selects the library default for the cloud size. */
+    int32_t n_vox;
+    /* Largest number of points per tile, 1..64.  A voxel with more points is
+     * split into consecutive tiles, each with its own enclosing sphere and
+     * its own voxel-level distance.  0 selects 64 (one wavefront). */
+    int32_t tile;
+    /* Workgroups of the persistent sampler, 1..256 and at most the number of
+     * compute units (all must be resident at once); 0 = one per compute unit. */
+    int32_t groups;
+    /* RFPS_F_* bits. */
+    uint32_t flags;
+} rfps_params;
+
+/* Handle to a voxel index built by rfps_build_index().  Plain data: it
+ * records where in the caller's workspace the index lives.  Nothing to free. */
+typedef struct rfps_index {
+    int32_t n;        /* points */
+    int32_t n_vox;    /* resolved voxel bins per axis */
+    int32_t tile;     /* resolved tile size */
+    int32_t reserved;
+    void *ws;         /* device workspace holding the index */
+    size_t ws_bytes;
+} rfps_index;
+
+/* Counters accumulated by a sampling call made with RFPS_F_TELEMETRY. */
+typedef struct rfps_telemetry {
+    int64_t iters;          /* update rounds after the initial one (m - 2 when m >= 2) */
+    int64_t tiles;          /* tiles in the index */
+    int64_t tile_tests;     /* sphere tests evaluated */
+    int64_t tiles_pruned;   /* tests that skipped the tile */
+    int64_t points_visited; /* points in tiles that were not skipped */
+    int64_t points_skipped; /* of those, removed by the point skip */
+    int64_t points_updated; /* strict decreases of a point's distance */
+    int64_t tiles_resynced; /* tiles whose voxel-level distance was recomputed */
+} rfps_telemetry;
+
+/* Shape of a built index, read back by rfps_read_index_info(). */
+typedef struct rfps_index_info {
+    int64_t n_voxels;  /* K, active voxels (Sec. 3.2) */
+    int64_t n_tiles;   /* tiles after splitting voxels larger than the tile size */
+    double pmin[3];    /* bounding-box minimum */
+    double voxel_edge; /* L of eq. voxel_size */
+} rfps_index_info;
+
+/*
+ * Bytes of device workspace that rfps_build_index() and rfps_sample() need
+ * for a cloud of n points with these parameters (NULL = defaults).  Returns 0
+ * if n < 1 or a parameter is out of range.  Host only; no device work.
+ */
+size_t rfps_index_workspace_size(int32_t n, const rfps_params *params);
+
+/*
+ * Builds the spherical-voxel index of a cloud (Sec. 3.2; the GPU steps of
+ * Algorithm 2: voxel mapping, sort by voxel id, gather to structure of
+ * arrays, active-voxel compaction), then splits voxels into tiles and
+ * computes each tile's enclosing sphere.
+ *   xyz      device, float32 [n][3], row-major (x, y, z of point i at 3i..3i+2).
+ *            Read only during this call's device work; the index keeps its
+ *            own copy, so xyz may be reused once that work has completed.
+ *   n        number of points, >= 1.
+ *   params   host, may be NULL (defaults).
+ *   ws       device workspace, 256-byte aligned, ws_bytes >=
+ *            rfps_index_workspace_size(n, params).
+ *   out      host; receives the handle.
+ * A non-finite coordinate is detected on the device (see rfps_read_status).
+ */
+rfps_status rfps_build_index(const float *xyz, int32_t n, const rfps_params *params, void *ws,
+                             size_t ws_bytes, void *stream, rfps_index *out);
+
+/*
+ * Exact FPS of the indexed cloud with spherical-voxel pruning (Sec. 3.3,
+ * Sec. 3.4): one persistent kernel runs all m - 1 selections.
+ *   index    host, a handle from rfps_build_index() whose work precedes this
+ *            call in stream order.
+ *   m        samples, 1 <= m <= n.
+ *   start    index of the first sample (the seed s_0), 0 <= start < n.
+ *   params   host, may be NULL; only `groups` and `flags` are read.
+ *   out_idx  device, int32 [m]: original indices of the samples in order.
+ *   out_d2   device, float32 [m] or NULL: out_d2[0] = +inf; out_d2[j] is the
+ *            squared distance of sample j to the nearest earlier sample.
+ * Calls on the same workspace must not overlap (they share its buffers).
+ */
+rfps_status rfps_sample(const rfps_index *index, int32_t m, int32_t start,
+                        const rfps_params *params, int32_t *out_idx, float *out_d2,
+                        void *stream);
+
+/* Waits for the stream, then returns the device-side status recorded in the
+ * index workspace by the last build or sampling call (RFPS_OK if none). */
+rfps_status rfps_read_status(const rfps_index *index, void *stream);
+
+/* Waits for the stream and copies the index shape into *out (host). */
+rfps_status rfps_read_index_info(const rfps_index *index, void *stream, rfps_index_info *out);
+
+/* Waits for the stream and copies the counters of the last sampling call
+ * made with RFPS_F_TELEMETRY into *out (host). */
+rfps_status rfps_read_telemetry(const rfps_index *index, void *stream, rfps_telemetry *out);
+
+/* Waits for the stream and copies up to `cap` per-iteration timestamps of
+ * the last sampling call made with RFPS_F_TRACE into the host array `out`:
+ * out[2j] is the time workgroup 0 published its candidate for selection j,
+ * out[2j+1] the time it knew the winner, in ticks of the device wall clock.
+ * *ticks_per_s receives that clock's rate.  Returns the number of pairs. */
+int32_t rfps_read_trace(const rfps_index *index, void *stream, uint64_t *out, int32_t cap,
+                        double *ticks_per_s);
+
+/*
+ * Plain FPS without any index (the comparison kernels):
+ *   variant 0: persistent, every workgroup keeps its share of the points and
+ *              of D in registers, one exchange per selection;
+ *   variant 1: one workgroup streams the whole cloud from device memory every
+ *              selection (the conventional GPU FPS kernel).
+ * Arguments as above; ws is device workspace of
+ * rfps_fps_plain_workspace_size(n, variant) bytes.  groups applies to
+ * variant 0 (0 = one per compute unit).
+ */
+size_t rfps_fps_plain_workspace_size(int32_t n, int32_t variant);
+rfps_status rfps_fps_plain(const float *xyz, int32_t n, int32_t m, int32_t start, int32_t variant,
+                           int32_t groups, void *ws, size_t ws_bytes, int32_t *out_idx,
+                           float *out_d2, void *stream);
+
+/* Waits for the stream, then returns the device-side status recorded in a
+ * plain-FPS workspace by the last rfps_fps_plain() call on it. */
+rfps_status rfps_read_plain_status(const void *ws, size_t ws_bytes, void *stream);
+
+/* Static description of a status code. */
+const char *rfps_status_str(rfps_status s);
+
+/* Default voxel bins per axis for a cloud of n points. */
+int32_t rfps_default_n_vox(int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RFPS_H */

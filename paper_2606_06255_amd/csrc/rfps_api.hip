@@ -1,0 +1,416 @@
+// C ABI of librfps (declared in include/rfps.h): argument validation,
+// workspace layout, device checks and the launch sequence of each call.
+// Host code only; the kernels live in index_build.hip, sample_rfps.hip and
+// sample_plain.hip.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+
+#include "rfps_internal.h"
+
+using namespace rfps;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr uint32_t kKnownFlags = RFPS_F_NO_PRUNE | RFPS_F_NO_POINT_SKIP | RFPS_F_TELEMETRY | RFPS_F_TRACE;
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct DeviceInfo {
+    bool probed = false;
+    bool ok = false;       // a gfx950 device with cooperative launch
+    int cus = 0;
+    int max_lds = 0;       // bytes of LDS one workgroup may use
+    double wall_hz = 0.0;  // rate of the device wall clock
+};
+
+std::mutex g_dev_mu;
+DeviceInfo g_dev[64];
+
+// Probes the current device once.  Returns nullptr when there is no device.
+const DeviceInfo *device_info()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return nullptr;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    DeviceInfo &d = g_dev[dev];
+    if (!d.probed) {
+        d.probed = true;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+            return nullptr;
+        int coop = 0, lds = 0, lds_optin = 0, clk = 0;
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin, dev);
+        hipDeviceGetAttribute(&clk, hipDeviceAttributeWallClockRate, dev);  // kHz
+        d.cus = prop.multiProcessorCount;
+        // gfx950 lets one workgroup opt in to the whole 160 KB LDS of a CU
+        d.max_lds = std::max(lds, lds_optin);
+        d.wall_hz = (double)clk * 1000.0;
+        d.ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0 && coop != 0 && d.cus > 0;
+    }
+    return &d;
+}
+
+// Index workspace layout.  Every segment is 256-byte aligned.
+struct IndexLayout {
+    size_t hdr, keyA, keyB, valA, valB, xs, ys, zs, inv, flags, hscan, vstart, tcount, tbase, tstart, tcnt, tcx,
+        tcy, tcz, trad, partials, hist, board, trace, total;
+    int radix_passes, nblk;
+};
+
+int bit_length(uint64_t v)
+{
+    int b = 0;
+    while (v) {
+        ++b;
+        v >>= 1;
+    }
+    return b;
+}
+
+IndexLayout layout_index(int n, int n_vox)
+{
+    IndexLayout L;
+    size_t cur = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = align_up(cur);
+        cur = o + bytes;
+        return o;
+    };
+    const size_t N = (size_t)n;
+    L.nblk = (n + kRadixTile - 1) / kRadixTile;
+    const uint64_t cells = (uint64_t)n_vox * n_vox * n_vox;
+    L.radix_passes = (bit_length(cells - 1) + 7) / 8;
+    const size_t scan_elems = std::max(N, (size_t)256 * L.nblk);
+    L.hdr = take(sizeof(IndexHeader));
+    L.keyA = take(4 * N);
+    L.keyB = take(4 * N);
+    L.valA = take(4 * N);
+    L.valB = take(4 * N);
+    L.xs = take(4 * N);
+    L.ys = take(4 * N);
+    L.zs = take(4 * N);
+    L.inv = take(4 * N);
+    L.flags = take(4 * N);
+    L.hscan = take(4 * N);
+    L.vstart = take(4 * (N + 1));
+    L.tcount = take(4 * N);
+    L.tbase = take(4 * N);
+    L.tstart = take(4 * N);
+    L.tcnt = take(4 * N);
+    L.tcx = take(4 * N);
+    L.tcy = take(4 * N);
+    L.tcz = take(4 * N);
+    L.trad = take(4 * N);
+    L.partials = take(4 * ((scan_elems + kScanChunk - 1) / kScanChunk + 1));
+    L.hist = take(4 * (size_t)256 * L.nblk);
+    L.board = take(8 * (size_t)2 * kMaxGroups * kSlotWords);
+    L.trace = take(8 * (size_t)2 * kTraceCap);
+    L.total = align_up(cur);
+    return L;
+}
+
+IndexView make_view(void *ws, int n, int n_vox, int tile)
+{
+    const IndexLayout L = layout_index(n, n_vox);
+    unsigned char *b = static_cast<unsigned char *>(ws);
+    IndexView v;
+    v.hdr = reinterpret_cast<IndexHeader *>(b + L.hdr);
+    v.keyA = reinterpret_cast<uint32_t *>(b + L.keyA);
+    v.keyB = reinterpret_cast<uint32_t *>(b + L.keyB);
+    v.valA = reinterpret_cast<uint32_t *>(b + L.valA);
+    v.valB = reinterpret_cast<uint32_t *>(b + L.valB);
+    const bool in_b = (L.radix_passes % 2) == 1;
+    v.skey = in_b ? v.keyB : v.keyA;
+    v.orig = in_b ? v.valB : v.valA;
+    v.xs = reinterpret_cast<float *>(b + L.xs);
+    v.ys = reinterpret_cast<float *>(b + L.ys);
+    v.zs = reinterpret_cast<float *>(b + L.zs);
+    v.inv = reinterpret_cast<uint32_t *>(b + L.inv);
+    v.flags = reinterpret_cast<uint32_t *>(b + L.flags);
+    v.hscan = reinterpret_cast<uint32_t *>(b + L.hscan);
+    v.vstart = reinterpret_cast<uint32_t *>(b + L.vstart);
+    v.tcount = reinterpret_cast<uint32_t *>(b + L.tcount);
+    v.tbase = reinterpret_cast<uint32_t *>(b + L.tbase);
+    v.tstart = reinterpret_cast<uint32_t *>(b + L.tstart);
+    v.tcnt = reinterpret_cast<uint32_t *>(b + L.tcnt);
+    v.tcx = reinterpret_cast<float *>(b + L.tcx);
+    v.tcy = reinterpret_cast<float *>(b + L.tcy);
+    v.tcz = reinterpret_cast<float *>(b + L.tcz);
+    v.trad = reinterpret_cast<float *>(b + L.trad);
+    v.partials = reinterpret_cast<uint32_t *>(b + L.partials);
+    v.hist = reinterpret_cast<uint32_t *>(b + L.hist);
+    v.board = reinterpret_cast<unsigned long long *>(b + L.board);
+    v.trace = reinterpret_cast<unsigned long long *>(b + L.trace);
+    v.n = n;
+    v.n_vox = n_vox;
+    v.tile = tile;
+    v.radix_passes = L.radix_passes;
+    return v;
+}
+
+bool params_valid(const rfps_params *p)
+{
+    if (!p)
+        return true;
+    return p->n_vox >= 0 && p->n_vox <= kMaxNVox && p->tile >= 0 && p->tile <= kWave && p->groups >= 0 &&
+           p->groups <= kMaxGroups && (p->flags & ~kKnownFlags) == 0;
+}
+
+int resolve_n_vox(int n, const rfps_params *p) { return (p && p->n_vox) ? p->n_vox : rfps_default_n_vox(n); }
+int resolve_tile(const rfps_params *p) { return (p && p->tile) ? p->tile : kWave; }
+
+bool aligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) % kAlign) == 0; }
+
+// Plain-FPS workspace: status word, exchange board, distance array.
+struct PlainLayout {
+    size_t status, board, dist, total;
+};
+PlainLayout layout_plain(int n)
+{
+    PlainLayout L;
+    L.status = 0;
+    L.board = align_up(16);
+    L.dist = align_up(L.board + 8 * (size_t)2 * kMaxGroups * kSlotWords);
+    L.total = align_up(L.dist + 4 * (size_t)n);
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t rfps_default_n_vox(int32_t n)
+{
+    static const int cand[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256};
+    const double target = sqrt((double)(n > 0 ? n : 1) / 40.0);
+    int best = cand[0];
+    for (int c : cand)
+        if (fabs(log((double)c / target)) < fabs(log((double)best / target)))
+            best = c;
+    return best;
+}
+
+const char *rfps_status_str(rfps_status s)
+{
+    switch (s) {
+    case RFPS_OK: return "ok";
+    case RFPS_ERR_INVALID_ARG: return "invalid argument";
+    case RFPS_ERR_NONFINITE: return "non-finite input coordinate";
+    case RFPS_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case RFPS_ERR_DEVICE: return "HIP runtime error";
+    case RFPS_ERR_UNSUPPORTED: return "unsupported device or launch shape";
+    case RFPS_ERR_CAPACITY: return "cloud share per workgroup exceeds the on-chip budget";
+    case RFPS_ERR_TIMEOUT: return "bounded wait in a persistent kernel expired";
+    }
+    return "unknown status";
+}
+
+size_t rfps_index_workspace_size(int32_t n, const rfps_params *params)
+{
+    if (n < 1 || n > kMaxPoints || !params_valid(params))
+        return 0;
+    return layout_index(n, resolve_n_vox(n, params)).total;
+}
+
+rfps_status rfps_build_index(const float *xyz, int32_t n, const rfps_params *params, void *ws, size_t ws_bytes,
+                             void *stream, rfps_index *out)
+{
+    if (!xyz || !out || n < 1 || n > kMaxPoints || !params_valid(params))
+        return RFPS_ERR_INVALID_ARG;
+    const int n_vox = resolve_n_vox(n, params);
+    const int tile = resolve_tile(params);
+    if (!ws || !aligned(ws) || ws_bytes < layout_index(n, n_vox).total)
+        return RFPS_ERR_WORKSPACE;
+    const DeviceInfo *d = device_info();
+    if (!d)
+        return RFPS_ERR_DEVICE;
+    if (!d->ok)
+        return RFPS_ERR_UNSUPPORTED;
+    const IndexView v = make_view(ws, n, n_vox, tile);
+    if (launch_build_index(v, xyz, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return RFPS_ERR_DEVICE;
+    out->n = n;
+    out->n_vox = n_vox;
+    out->tile = tile;
+    out->reserved = 0;
+    out->ws = ws;
+    out->ws_bytes = ws_bytes;
+    return RFPS_OK;
+}
+
+static rfps_status check_index(const rfps_index *index)
+{
+    if (!index || index->n < 1 || index->n > kMaxPoints || index->n_vox < 1 || index->n_vox > kMaxNVox ||
+        index->tile < 1 || index->tile > kWave)
+        return RFPS_ERR_INVALID_ARG;
+    if (!index->ws || !aligned(index->ws) || index->ws_bytes < layout_index(index->n, index->n_vox).total)
+        return RFPS_ERR_WORKSPACE;
+    return RFPS_OK;
+}
+
+rfps_status rfps_sample(const rfps_index *index, int32_t m, int32_t start, const rfps_params *params,
+                        int32_t *out_idx, float *out_d2, void *stream)
+{
+    rfps_status st = check_index(index);
+    if (st != RFPS_OK)
+        return st;
+    if (m < 1 || m > index->n || start < 0 || start >= index->n || !out_idx || !params_valid(params))
+        return RFPS_ERR_INVALID_ARG;
+    const DeviceInfo *d = device_info();
+    if (!d)
+        return RFPS_ERR_DEVICE;
+    if (!d->ok)
+        return RFPS_ERR_UNSUPPORTED;
+    SampleLaunch L;
+    L.G = (params && params->groups) ? params->groups : std::min(d->cus, kMaxGroups);
+    L.flags = params ? params->flags : 0u;
+    const size_t stat = rfps_sampler_static_lds();
+    if (stat == 0 || (size_t)d->max_lds <= stat + 1024)
+        return RFPS_ERR_UNSUPPORTED;
+    L.lds_budget = (uint32_t)((d->max_lds - stat - 256) & ~(size_t)255);
+    if (L.G > d->cus)
+        return RFPS_ERR_UNSUPPORTED;
+    const IndexView v = make_view(index->ws, index->n, index->n_vox, index->tile);
+    hipError_t e = launch_rfps_sample(v, m, start, L, out_idx, out_d2, static_cast<hipStream_t>(stream));
+    if (e == hipErrorCooperativeLaunchTooLarge)
+        return RFPS_ERR_UNSUPPORTED;
+    return e == hipSuccess ? RFPS_OK : RFPS_ERR_DEVICE;
+}
+
+rfps_status rfps_read_status(const rfps_index *index, void *stream)
+{
+    rfps_status st = check_index(index);
+    if (st != RFPS_OK)
+        return st;
+    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess)
+        return RFPS_ERR_DEVICE;
+    uint32_t w[2];
+    if (hipMemcpy(w, index->ws, sizeof w, hipMemcpyDeviceToHost) != hipSuccess)
+        return RFPS_ERR_DEVICE;
+    return (rfps_status)(w[0] ? w[0] : w[1]);
+}
+
+rfps_status rfps_read_index_info(const rfps_index *index, void *stream, rfps_index_info *out)
+{
+    rfps_status st = check_index(index);
+    if (st != RFPS_OK)
+        return st;
+    if (!out)
+        return RFPS_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess)
+        return RFPS_ERR_DEVICE;
+    IndexHeader h;
+    if (hipMemcpy(&h, index->ws, sizeof h, hipMemcpyDeviceToHost) != hipSuccess)
+        return RFPS_ERR_DEVICE;
+    out->n_voxels = h.n_voxels;
+    out->n_tiles = h.n_tiles;
+    for (int a = 0; a < 3; ++a)
+        out->pmin[a] = h.pmin[a];
+    out->voxel_edge = h.L;
+    return RFPS_OK;
+}
+
+rfps_status rfps_read_telemetry(const rfps_index *index, void *stream, rfps_telemetry *out)
+{
+    rfps_status st = check_index(index);
+    if (st != RFPS_OK)
+        return st;
+    if (!out)
+        return RFPS_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess)
+        return RFPS_ERR_DEVICE;
+    IndexHeader h;
+    if (hipMemcpy(&h, index->ws, sizeof h, hipMemcpyDeviceToHost) != hipSuccess)
+        return RFPS_ERR_DEVICE;
+    static_assert(sizeof(rfps_telemetry) == 8 * sizeof(unsigned long long), "telemetry layout");
+    memcpy(out, h.tele, sizeof *out);
+    return RFPS_OK;
+}
+
+int32_t rfps_read_trace(const rfps_index *index, void *stream, uint64_t *out, int32_t cap, double *ticks_per_s)
+{
+    if (check_index(index) != RFPS_OK || !out || cap < 0)
+        return -1;
+    const DeviceInfo *d = device_info();
+    if (!d || hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess)
+        return -1;
+    IndexHeader h;
+    if (hipMemcpy(&h, index->ws, sizeof h, hipMemcpyDeviceToHost) != hipSuccess)
+        return -1;
+    int32_t cnt = h.last_m > 1 ? (int32_t)h.last_m - 1 : 0;
+    cnt = std::min(std::min(cnt, cap), kTraceCap);
+    const IndexLayout L = layout_index(index->n, index->n_vox);
+    if (cnt > 0 && hipMemcpy(out, static_cast<unsigned char *>(index->ws) + L.trace, 16 * (size_t)cnt,
+                             hipMemcpyDeviceToHost) != hipSuccess)
+        return -1;
+    if (ticks_per_s)
+        *ticks_per_s = d->wall_hz;
+    return cnt;
+}
+
+size_t rfps_fps_plain_workspace_size(int32_t n, int32_t variant)
+{
+    if (n < 1 || n > kMaxPoints || variant < 0 || variant > 1)
+        return 0;
+    return layout_plain(n).total;
+}
+
+rfps_status rfps_fps_plain(const float *xyz, int32_t n, int32_t m, int32_t start, int32_t variant, int32_t groups,
+                           void *ws, size_t ws_bytes, int32_t *out_idx, float *out_d2, void *stream)
+{
+    if (!xyz || !out_idx || n < 1 || n > kMaxPoints || m < 1 || m > n || start < 0 || start >= n || variant < 0 ||
+        variant > 1 || groups < 0 || groups > kMaxGroups)
+        return RFPS_ERR_INVALID_ARG;
+    const PlainLayout PL = layout_plain(n);
+    if (!ws || !aligned(ws) || ws_bytes < PL.total)
+        return RFPS_ERR_WORKSPACE;
+    const DeviceInfo *d = device_info();
+    if (!d)
+        return RFPS_ERR_DEVICE;
+    if (!d->ok)
+        return RFPS_ERR_UNSUPPORTED;
+    PlainLaunch L;
+    L.variant = variant;
+    L.G = 1;
+    L.ppt = 1;
+    if (variant == 0) {
+        const int max_g = std::min(d->cus, kMaxGroups);
+        L.G = groups ? groups : std::max(1, std::min(max_g, (n + kBlock * 8 - 1) / (kBlock * 8)));
+        if (L.G > d->cus)
+            return RFPS_ERR_UNSUPPORTED;
+        const long long per_thread = ((long long)n + (long long)L.G * kBlock - 1) / ((long long)L.G * kBlock);
+        while (L.ppt < per_thread)
+            L.ppt <<= 1;
+        if (L.ppt > 32)
+            return RFPS_ERR_CAPACITY;
+    }
+    unsigned char *b = static_cast<unsigned char *>(ws);
+    hipError_t e = launch_fps_plain(xyz, n, m, start, L, reinterpret_cast<uint32_t *>(b + PL.status),
+                                    reinterpret_cast<unsigned long long *>(b + PL.board),
+                                    reinterpret_cast<float *>(b + PL.dist), out_idx, out_d2,
+                                    static_cast<hipStream_t>(stream));
+    if (e == hipErrorCooperativeLaunchTooLarge)
+        return RFPS_ERR_UNSUPPORTED;
+    return e == hipSuccess ? RFPS_OK : RFPS_ERR_DEVICE;
+}
+
+rfps_status rfps_read_plain_status(const void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ws || !aligned(ws) || ws_bytes < layout_plain(1).total)
+        return RFPS_ERR_WORKSPACE;
+    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess)
+        return RFPS_ERR_DEVICE;
+    uint32_t w = 0;
+    if (hipMemcpy(&w, ws, sizeof w, hipMemcpyDeviceToHost) != hipSuccess)
+        return RFPS_ERR_DEVICE;
+    return (rfps_status)w;
+}
+
+}  // extern "C"
