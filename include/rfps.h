@@ -48,14 +48,16 @@ typedef enum rfps_status {
     RFPS_ERR_DEVICE = 4,      /* a HIP runtime call failed */
     RFPS_ERR_UNSUPPORTED = 5, /* no usable gfx950 device, or a launch shape it cannot run */
     RFPS_ERR_CAPACITY = 6,    /* the cloud's share per workgroup exceeds the on-chip budget */
-    RFPS_ERR_TIMEOUT = 7      /* a bounded wait inside a persistent kernel expired */
+    RFPS_ERR_TIMEOUT = 7,     /* a bounded wait inside a persistent kernel expired */
+    RFPS_ERR_INTERNAL = 8     /* an internal consistency check of a kernel failed */
 } rfps_status;
 
 /* rfps_params.flags */
-#define RFPS_F_NO_PRUNE 0x01u      /* visit every tile each iteration (no voxel pruning) */
+#define RFPS_F_NO_PRUNE 0x01u      /* visit every tile each iteration (no voxel pruning); one-pick sampler */
 #define RFPS_F_NO_POINT_SKIP 0x02u /* no coordinate-wise point skip (Sec. 3.4.3) */
 #define RFPS_F_TELEMETRY 0x04u     /* count tests, prunes, visits and updates */
-#define RFPS_F_TRACE 0x08u         /* time every iteration of workgroup 0 */
+#define RFPS_F_TRACE 0x08u         /* time every exchange of workgroup 0 */
+#define RFPS_F_SINGLE_PICK 0x10u   /* one selection per exchange (no multi-pick rounds) */
 
 typedef struct rfps_params {
     /* Voxel bins per axis, n_vox of eq. voxel_size (Sec. 3.2); 1..1024.
@@ -68,6 +70,10 @@ typedef struct rfps_params {
     /* Workgroups of the persistent sampler, 1..256 and at most the number of
      * compute units (all must be resident at once); 0 = one per compute unit. */
     int32_t groups;
+    /* Lookahead depth of the multi-pick sampler: every workgroup proposes
+     * this many local candidates per exchange round; 2, 4 or 8 (0 = 4).
+     * Output-neutral, like n_vox, tile and groups. */
+    int32_t lookahead;
     /* RFPS_F_* bits. */
     uint32_t flags;
 } rfps_params;
@@ -93,6 +99,15 @@ typedef struct rfps_telemetry {
     int64_t points_skipped; /* of those, removed by the point skip */
     int64_t points_updated; /* strict decreases of a point's distance */
     int64_t tiles_resynced; /* tiles whose voxel-level distance was recomputed */
+    int64_t exchanges;      /* exchange rounds (m - 1 for the one-pick sampler) */
+    /* wall-clock ticks workgroup 0 of the multi-pick sampler spent in each
+     * phase of its rounds: local lookahead, exchange, merge, apply */
+    int64_t ticks_lookahead;
+    int64_t ticks_exchange;
+    int64_t ticks_merge;
+    int64_t ticks_apply;
+    int64_t tick_hz;        /* rate of those ticks (filled in by the reader) */
+    int64_t reserved[2];
 } rfps_telemetry;
 
 /* Shape of a built index, read back by rfps_read_index_info(). */
@@ -130,7 +145,12 @@ rfps_status rfps_build_index(const float *xyz, int32_t n, const rfps_params *par
 
 /*
  * Exact FPS of the indexed cloud with spherical-voxel pruning (Sec. 3.3,
- * Sec. 3.4): one persistent kernel runs all m - 1 selections.
+ * Sec. 3.4): one persistent kernel runs all m - 1 selections.  By default
+ * each exchange between workgroups settles a whole round of selections
+ * (certified multi-pick: every workgroup proposes `lookahead` candidates
+ * from its own points and all workgroups replay the same exact merge);
+ * RFPS_F_SINGLE_PICK exchanges once per selection instead.  Both return the
+ * plain FPS sequence bit for bit.
  *   index    host, a handle from rfps_build_index() whose work precedes this
  *            call in stream order.
  *   m        samples, 1 <= m <= n.
@@ -158,9 +178,13 @@ rfps_status rfps_read_telemetry(const rfps_index *index, void *stream, rfps_tele
 
 /* Waits for the stream and copies up to `cap` per-iteration timestamps of
  * the last sampling call made with RFPS_F_TRACE into the host array `out`:
- * out[2j] is the time workgroup 0 published its candidate for selection j,
- * out[2j+1] the time it knew the winner, in ticks of the device wall clock.
- * *ticks_per_s receives that clock's rate.  Returns the number of pairs. */
+ * one pair per exchange (per selection for the one-pick sampler, per round
+ * for the multi-pick sampler): out[2k] is the time workgroup 0 published
+ * its candidates for exchange k, out[2k+1] the time it knew the outcome, in
+ * ticks of the device wall clock; for the multi-pick sampler the top 16 bits
+ * of out[2k+1] hold the number of selections the round settled (mask them
+ * off before using the time).  *ticks_per_s receives the clock's rate.
+ * Returns the number of pairs. */
 int32_t rfps_read_trace(const rfps_index *index, void *stream, uint64_t *out, int32_t cap,
                         double *ticks_per_s);
 

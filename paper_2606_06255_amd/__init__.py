@@ -20,17 +20,19 @@ RFPS_OK = 0
 STATUS_NAMES = {
     0: "RFPS_OK", 1: "RFPS_ERR_INVALID_ARG", 2: "RFPS_ERR_NONFINITE", 3: "RFPS_ERR_WORKSPACE",
     4: "RFPS_ERR_DEVICE", 5: "RFPS_ERR_UNSUPPORTED", 6: "RFPS_ERR_CAPACITY", 7: "RFPS_ERR_TIMEOUT",
+    8: "RFPS_ERR_INTERNAL",
 }
 F_NO_PRUNE = 0x01
 F_NO_POINT_SKIP = 0x02
 F_TELEMETRY = 0x04
 F_TRACE = 0x08
+F_SINGLE_PICK = 0x10
 WS_ALIGN = 256
 
 
 class rfps_params(ctypes.Structure):
     _fields_ = [("n_vox", ctypes.c_int32), ("tile", ctypes.c_int32), ("groups", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("lookahead", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
 class rfps_index(ctypes.Structure):
@@ -41,10 +43,11 @@ class rfps_index(ctypes.Structure):
 class rfps_telemetry(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "iters", "tiles", "tile_tests", "tiles_pruned", "points_visited", "points_skipped",
-        "points_updated", "tiles_resynced")]
+        "points_updated", "tiles_resynced", "exchanges", "ticks_lookahead", "ticks_exchange",
+        "ticks_merge", "ticks_apply", "tick_hz", "reserved0", "reserved1")]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if not k.startswith("reserved")}
 
 
 class rfps_index_info(ctypes.Structure):
@@ -121,8 +124,8 @@ def _check_xyz(xyz: torch.Tensor):
         raise ValueError("xyz must be a contiguous float32 CUDA tensor of shape [N, 3]")
 
 
-def _params(n_vox=0, tile=0, groups=0, flags=0) -> rfps_params:
-    return rfps_params(int(n_vox), int(tile), int(groups), int(flags))
+def _params(n_vox=0, tile=0, groups=0, flags=0, lookahead=0) -> rfps_params:
+    return rfps_params(int(n_vox), int(tile), int(groups), int(lookahead), int(flags))
 
 
 def default_n_vox(n: int) -> int:
@@ -151,8 +154,12 @@ def index_workspace_size(n: int, n_vox: int = 0, tile: int = 0) -> int:
     return int(lib().rfps_index_workspace_size(int(n), ctypes.byref(p)))
 
 
-def build_index(xyz: torch.Tensor, n_vox: int = 0, tile: int = 0) -> Index:
-    """rfps_build_index on torch's current stream."""
+def build_index(xyz: torch.Tensor, n_vox: int = 0, tile: int = 0, reuse: Index | None = None) -> Index:
+    """rfps_build_index on torch's current stream.
+
+    With `reuse`, the workspace of that index is rebuilt in place when it is
+    large enough (the old index is then invalid); nothing is allocated.
+    """
     _check_xyz(xyz)
     L = lib()
     n = xyz.shape[0]
@@ -160,14 +167,19 @@ def build_index(xyz: torch.Tensor, n_vox: int = 0, tile: int = 0) -> Index:
     nbytes = L.rfps_index_workspace_size(n, ctypes.byref(p))
     if nbytes == 0:
         raise RfpsError(1, "rfps_index_workspace_size")
-    ws, ptr = _workspace(nbytes, xyz.device)
+    if reuse is not None and reuse.ws_bytes >= nbytes and reuse.device == xyz.device:
+        ws, ptr, nbytes = reuse.ws, reuse.ws_ptr, reuse.ws_bytes
+    else:
+        ws, ptr = _workspace(nbytes, xyz.device)
     h = rfps_index()
     _check(L.rfps_build_index(xyz.data_ptr(), n, ctypes.byref(p), ptr, nbytes, _stream(xyz.device),
                               ctypes.byref(h)), "rfps_build_index")
-    return Index(h, ws, xyz.device)
+    idx = Index(h, ws, xyz.device)
+    idx.ws_ptr, idx.ws_bytes = ptr, nbytes
+    return idx
 
 
-def sample(index: Index, m: int, start: int = 0, groups: int = 0, flags: int = 0,
+def sample(index: Index, m: int, start: int = 0, groups: int = 0, flags: int = 0, lookahead: int = 0,
            out_idx: torch.Tensor | None = None, out_d2: torch.Tensor | None = None):
     """rfps_sample: returns (idx int32 [m], d2 float32 [m]) on the index's device."""
     dev = index.device
@@ -175,7 +187,7 @@ def sample(index: Index, m: int, start: int = 0, groups: int = 0, flags: int = 0
         out_idx = torch.empty(m, dtype=torch.int32, device=dev)
     if out_d2 is None:
         out_d2 = torch.empty(m, dtype=torch.float32, device=dev)
-    p = _params(0, 0, groups, flags)
+    p = _params(0, 0, groups, flags, lookahead)
     _check(lib().rfps_sample(ctypes.byref(index.handle), int(m), int(start), ctypes.byref(p),
                              out_idx.data_ptr(), out_d2.data_ptr(), _stream(dev)), "rfps_sample")
     return out_idx, out_d2
@@ -213,10 +225,10 @@ def read_trace(index: Index, cap: int = 1 << 17):
 
 
 def fps(xyz: torch.Tensor, m: int, start: int = 0, n_vox: int = 0, tile: int = 0, groups: int = 0,
-        flags: int = 0):
+        flags: int = 0, lookahead: int = 0):
     """Build the index and sample: exact FPS with spherical-voxel pruning."""
     idx = build_index(xyz, n_vox=n_vox, tile=tile)
-    out = sample(idx, m, start, groups=groups, flags=flags)
+    out = sample(idx, m, start, groups=groups, flags=flags, lookahead=lookahead)
     st = read_status(idx)
     _check(st, "device status")
     return out

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librfps.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["rfps_api.hip", "index_build.hip", "sample_rfps.hip", "sample_plain.hip"]
+SOURCES = ["rfps_api.hip", "index_build.hip", "sample_rfps.hip", "sample_rounds.hip", "sample_plain.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -45,6 +45,14 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (r.stdout, r.stderr))
     os.replace(tmp, LIB)
+    # native driver of the C ABI (profiling without Python in the process)
+    exe = os.path.join(PKG, "rfps_bench")
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O2", "-std=c++17", "-o", exe + ".tmp",
+           os.path.join(CSRC, "rfps_bench.cpp"), "-L" + PKG, "-lrfps", "-Wl,-rpath,$ORIGIN"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("rfps_bench failed to build:\n%s\n%s" % (r.stdout, r.stderr))
+    os.replace(exe + ".tmp", exe)
     if verbose:
         print("built", LIB)
     return LIB

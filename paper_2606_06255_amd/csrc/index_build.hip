@@ -26,8 +26,9 @@ __global__ void k_build_reset(IndexHeader *hdr)
             hdr->bb[a] = 0xffffffffu;  // running minimum
             hdr->bb[3 + a] = 0u;       // running maximum
         }
-        for (int t = 0; t < 8; ++t)
+        for (int t = 0; t < kTeleFields; ++t)
             hdr->tele[t] = 0;
+        hdr->trace_n = 0;
     }
 }
 
@@ -45,21 +46,39 @@ __global__ __launch_bounds__(kBlock) void k_bbox(const float *__restrict__ xyz, 
             mx[a] = fmaxf(mx[a], v);
         }
     }
+    // wave, then workgroup reduction; one atomic per bound per workgroup
+    __shared__ float s_mn[3][kWavesPerBlock], s_mx[3][kWavesPerBlock];
+    __shared__ uint32_t s_bad;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (threadIdx.x == 0)
+        s_bad = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         mn[a] = wave_min_f32(mn[a]);
         mx[a] = wave_max_f32(mx[a]);
-    }
-    if ((threadIdx.x & (kWave - 1)) == 0) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (mn[a] <= mx[a]) {
-                atomicMin(&hdr->bb[a], f2ord(mn[a]));
-                atomicMax(&hdr->bb[3 + a], f2ord(mx[a]));
-            }
+        if (lane == 0) {
+            s_mn[a][w] = mn[a];
+            s_mx[a][w] = mx[a];
         }
     }
-    if (__any(bad) && (threadIdx.x & (kWave - 1)) == 0)
+    const bool wave_bad = __any(bad);
+    __syncthreads();
+    if (wave_bad && lane == 0)
+        s_bad = 1;
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int a = threadIdx.x;
+        float lo = s_mn[a][0], hi = s_mx[a][0];
+        for (int q = 1; q < kWavesPerBlock; ++q) {
+            lo = fminf(lo, s_mn[a][q]);
+            hi = fmaxf(hi, s_mx[a][q]);
+        }
+        if (lo <= hi) {
+            atomicMin(&hdr->bb[a], f2ord(lo));
+            atomicMax(&hdr->bb[3 + a], f2ord(hi));
+        }
+    }
+    if (threadIdx.x == 0 && s_bad)
         set_status(&hdr->build_status, RFPS_ERR_NONFINITE);
 }
 
@@ -393,7 +412,7 @@ hipError_t launch_build_index(const IndexView &v, const float *xyz, hipStream_t 
 {
     const int n = v.n;
     k_build_reset<<<1, kWave, 0, s>>>(v.hdr);
-    k_bbox<<<std::min(blocks_for(n, kBlock), 2048), kBlock, 0, s>>>(xyz, n, v.hdr);
+    k_bbox<<<std::min(blocks_for(n, kBlock * 4), 512), kBlock, 0, s>>>(xyz, n, v.hdr);
     k_grid<<<1, kWave, 0, s>>>(v.hdr, v.n_vox);
     k_voxel_key<<<blocks_for(n, kBlock), kBlock, 0, s>>>(xyz, n, v.hdr, v.n_vox, v.keyA, v.valA);
     hipError_t e = hipGetLastError();

@@ -15,7 +15,9 @@ using namespace rfps;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr uint32_t kKnownFlags = RFPS_F_NO_PRUNE | RFPS_F_NO_POINT_SKIP | RFPS_F_TELEMETRY | RFPS_F_TRACE;
+constexpr uint32_t kKnownFlags =
+    RFPS_F_NO_PRUNE | RFPS_F_NO_POINT_SKIP | RFPS_F_TELEMETRY | RFPS_F_TRACE | RFPS_F_SINGLE_PICK;
+constexpr int kDefaultLookahead = 4;
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -110,7 +112,7 @@ IndexLayout layout_index(int n, int n_vox)
     L.trad = take(4 * N);
     L.partials = take(4 * ((scan_elems + kScanChunk - 1) / kScanChunk + 1));
     L.hist = take(4 * (size_t)256 * L.nblk);
-    L.board = take(8 * (size_t)2 * kMaxGroups * kSlotWords);
+    L.board = take(8 * (size_t)kBoardWords);
     L.trace = take(8 * (size_t)2 * kTraceCap);
     L.total = align_up(cur);
     return L;
@@ -160,7 +162,8 @@ bool params_valid(const rfps_params *p)
     if (!p)
         return true;
     return p->n_vox >= 0 && p->n_vox <= kMaxNVox && p->tile >= 0 && p->tile <= kWave && p->groups >= 0 &&
-           p->groups <= kMaxGroups && (p->flags & ~kKnownFlags) == 0;
+           p->groups <= kMaxGroups && (p->flags & ~kKnownFlags) == 0 &&
+           (p->lookahead == 0 || p->lookahead == 2 || p->lookahead == 4 || p->lookahead == 8);
 }
 
 int resolve_n_vox(int n, const rfps_params *p) { return (p && p->n_vox) ? p->n_vox : rfps_default_n_vox(n); }
@@ -177,7 +180,7 @@ PlainLayout layout_plain(int n)
     PlainLayout L;
     L.status = 0;
     L.board = align_up(16);
-    L.dist = align_up(L.board + 8 * (size_t)2 * kMaxGroups * kSlotWords);
+    L.dist = align_up(L.board + 8 * (size_t)kBoardWords);
     L.total = align_up(L.dist + 4 * (size_t)n);
     return L;
 }
@@ -208,6 +211,7 @@ const char *rfps_status_str(rfps_status s)
     case RFPS_ERR_UNSUPPORTED: return "unsupported device or launch shape";
     case RFPS_ERR_CAPACITY: return "cloud share per workgroup exceeds the on-chip budget";
     case RFPS_ERR_TIMEOUT: return "bounded wait in a persistent kernel expired";
+    case RFPS_ERR_INTERNAL: return "internal consistency check failed";
     }
     return "unknown status";
 }
@@ -271,7 +275,11 @@ rfps_status rfps_sample(const rfps_index *index, int32_t m, int32_t start, const
     SampleLaunch L;
     L.G = (params && params->groups) ? params->groups : std::min(d->cus, kMaxGroups);
     L.flags = params ? params->flags : 0u;
-    const size_t stat = rfps_sampler_static_lds();
+    // the multi-pick sampler is the default; plain (unpruned) sampling and an
+    // explicit request use one selection per exchange
+    const bool single = (L.flags & (RFPS_F_SINGLE_PICK | RFPS_F_NO_PRUNE)) != 0;
+    L.R = single ? 0 : ((params && params->lookahead) ? params->lookahead : kDefaultLookahead);
+    const size_t stat = rfps_sampler_static_lds(L.R);
     if (stat == 0 || (size_t)d->max_lds <= stat + 1024)
         return RFPS_ERR_UNSUPPORTED;
     L.lds_budget = (uint32_t)((d->max_lds - stat - 256) & ~(size_t)255);
@@ -329,8 +337,10 @@ rfps_status rfps_read_telemetry(const rfps_index *index, void *stream, rfps_tele
     IndexHeader h;
     if (hipMemcpy(&h, index->ws, sizeof h, hipMemcpyDeviceToHost) != hipSuccess)
         return RFPS_ERR_DEVICE;
-    static_assert(sizeof(rfps_telemetry) == 8 * sizeof(unsigned long long), "telemetry layout");
+    static_assert(sizeof(rfps_telemetry) == kTeleFields * sizeof(unsigned long long), "telemetry layout");
     memcpy(out, h.tele, sizeof *out);
+    const DeviceInfo *d = device_info();
+    out->tick_hz = d ? (int64_t)d->wall_hz : 0;
     return RFPS_OK;
 }
 
@@ -344,7 +354,7 @@ int32_t rfps_read_trace(const rfps_index *index, void *stream, uint64_t *out, in
     IndexHeader h;
     if (hipMemcpy(&h, index->ws, sizeof h, hipMemcpyDeviceToHost) != hipSuccess)
         return -1;
-    int32_t cnt = h.last_m > 1 ? (int32_t)h.last_m - 1 : 0;
+    int32_t cnt = (int32_t)h.trace_n;
     cnt = std::min(std::min(cnt, cap), kTraceCap);
     const IndexLayout L = layout_index(index->n, index->n_vox);
     if (cnt > 0 && hipMemcpy(out, static_cast<unsigned char *>(index->ws) + L.trace, 16 * (size_t)cnt,

@@ -19,6 +19,8 @@ constexpr int kBlock = 256;          // threads per workgroup of the persistent 
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kMaxGroups = 256;      // one exchange slot per thread of a workgroup
 constexpr int kSlotWords = 5;        // d2, ~orig, x, y, z, each tagged with the epoch
+constexpr int kMaxSlotWords = 64;    // largest slot of any exchange protocol (words)
+constexpr int kBoardWords = 2 * kMaxGroups * kMaxSlotWords;
 constexpr int kMaxNVox = 1024;
 constexpr int kMaxPoints = 1 << 26;
 constexpr int kRadixItems = 8;       // keys per thread per radix tile
@@ -26,6 +28,14 @@ constexpr int kRadixTile = kBlock * kRadixItems;
 constexpr int kScanItems = 16;       // elements per thread of the scan kernels
 constexpr int kScanChunk = kBlock * kScanItems;
 constexpr int kTraceCap = 1 << 17;   // iterations recorded by RFPS_F_TRACE
+constexpr int kTeleFields = 16;
+// telemetry slots (rfps_telemetry field order)
+constexpr int kTeleExchanges = 8;
+constexpr int kTeleTicksLookahead = 9;
+constexpr int kTeleTicksExchange = 10;
+constexpr int kTeleTicksMerge = 11;
+constexpr int kTeleTicksApply = 12;
+constexpr int kTeleTickHz = 13;
 
 // Status words live in the index header.  The build status is sticky for the
 // index; the sample status is cleared at the start of every sampling call.
@@ -36,10 +46,10 @@ struct IndexHeader {
     uint32_t n_tiles;    // tiles
     uint32_t bb[6];      // order-preserving encodings of min xyz, max xyz
     uint32_t last_m;     // m of the last sampling call
-    uint32_t pad;
+    uint32_t trace_n;    // entries the last traced call recorded
     double pmin[3];
     double L;            // voxel edge (eq. voxel_size)
-    unsigned long long tele[8];  // rfps_telemetry, in its field order
+    unsigned long long tele[kTeleFields];  // rfps_telemetry, in its field order
 };
 
 // Device pointers into an index workspace (see layout_index in rfps_api.hip).
@@ -56,7 +66,7 @@ struct IndexView {
     float *tcx, *tcy, *tcz, *trad;        // tile sphere centre and radius (rounded up)
     uint32_t *partials;                   // scan partial sums
     uint32_t *hist;                       // radix histograms [256][blocks]
-    unsigned long long *board;            // exchange board [2][kMaxGroups][kSlotWords]
+    unsigned long long *board;            // exchange board, kBoardWords words
     unsigned long long *trace;            // [kTraceCap][2]
     int32_t n, n_vox, tile, radix_passes;
 };
@@ -93,12 +103,58 @@ __device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsig
     return a > b ? a : b;
 }
 
+// Wave64 reductions on DPP lane permutes (no LDS round trip): quad swaps,
+// half-row and row mirrors combine each 16-lane row, then the row_bcast15 /
+// row_bcast31 broadcasts of GFX9 fold rows 0-1 into 2-3, leaving the result
+// in lane 63.  They must be called with all 64 lanes active.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t old, uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, 0xf, false);
+}
+constexpr int kDppQuadSwap1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int kDppQuadSwap2 = 0x4E;  // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppRowMirror = 0x140;
+constexpr int kDppBcast15 = 0x142;
+constexpr int kDppBcast31 = 0x143;
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+    v = max(v, dpp_u32<kDppQuadSwap1>(v, v));
+    v = max(v, dpp_u32<kDppQuadSwap2>(v, v));
+    v = max(v, dpp_u32<kDppHalfMirror>(v, v));
+    v = max(v, dpp_u32<kDppRowMirror>(v, v));
+    v = max(v, dpp_u32<kDppBcast15, 0xa>(v, v));
+    v = max(v, dpp_u32<kDppBcast31, 0xc>(v, v));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
+{
+    v = min(v, dpp_u32<kDppQuadSwap1>(v, v));
+    v = min(v, dpp_u32<kDppQuadSwap2>(v, v));
+    v = min(v, dpp_u32<kDppHalfMirror>(v, v));
+    v = min(v, dpp_u32<kDppRowMirror>(v, v));
+    v = min(v, dpp_u32<kDppBcast15, 0xa>(v, v));
+    v = min(v, dpp_u32<kDppBcast31, 0xc>(v, v));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Largest 64-bit key of the wave: the largest high half first, then the
+// largest low half among the lanes that hold it.
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1)
-        v = umax64(v, __shfl_xor(v, off, kWave));
-    return v;
+    const uint32_t hi = (uint32_t)(v >> 32);
+    const uint32_t mhi = wave_max_u32(hi);
+    const uint32_t mlo = wave_max_u32(hi == mhi ? (uint32_t)v : 0u);
+    return ((unsigned long long)mhi << 32) | mlo;
+}
+
+// Minimum of non-negative floats (distances, +inf allowed): their bit
+// patterns order like the values.
+__device__ __forceinline__ float wave_min_dist(float v)
+{
+    return __uint_as_float(wave_min_u32(__float_as_uint(v)));
 }
 
 __device__ __forceinline__ float wave_min_f32(float v)
@@ -152,6 +208,37 @@ __device__ __forceinline__ void set_status(uint32_t *word, uint32_t code)
                                          __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Pruning threshold of a tile with radius R (rounded up) and Dist_v = dv.
+//
+// Skipping the tile for sample s is safe when the FP32 value
+// q = fl32(||s - c||^2), computed with the same formula as a point distance,
+// satisfies q >= thr.  Derivation: q <= (1 + 2^-24)^5 ||s - c||^2, so
+// q >= thr implies ||s - c|| >= R + sqrt(dv / (1 - 2^-20)); by the triangle
+// inequality (eq. triangle_inequality_bound) every member p then has
+// ||p - s||^2 >= dv / (1 - 2^-20), and its FP32 squared distance, at least
+// (1 - 2^-24)^5 ||p - s||^2, is >= dv >= Dist_p[p]: the strict update cannot
+// fire (eq. radius_pruning_correctness).  The FP64 steps below are rounded
+// up by relative margins far above their rounding error.  dv == 0 means
+// nothing can decrease (thr = 0 always skips); dv below 2^-100 or above
+// 2^100 returns NaN, which never skips.
+__device__ __forceinline__ float prune_threshold(float R, float dv)
+{
+    if (dv == 0.0f)
+        return 0.0f;
+    if (!(dv >= 0x1p-100f) || !(dv <= 0x1p100f))
+        return __uint_as_float(0x7fc00000u);
+    double q = (double)R + sqrt((double)dv / (1.0 - 0x1p-20));
+    q *= 1.0 + 0x1p-50;
+    double T = q * q * (1.0 + 0x1p-50);
+    double t64 = T * (1.0 + 0x1p-20);
+    if (!(t64 <= 3.0e38))
+        return __uint_as_float(0x7fc00000u);
+    float thr = (float)t64;
+    if ((double)thr < t64)
+        thr = nextafterf(thr, INFINITY);
+    return thr;
+}
+
 // ---------------------------------------------------------------------------
 // Exchange board of the persistent kernels.
 //
@@ -171,9 +258,30 @@ struct Candidate {
     float x, y, z;
 };
 
+// Slots are padded to one 64-byte line so that workgroups polling different
+// slots never contend for the same line.
+constexpr int kSlotStride = 8;
+
 __device__ __forceinline__ unsigned long long *slot_ptr(unsigned long long *board, int G, uint32_t epoch, int g)
 {
-    return board + ((size_t)(epoch & 1u) * G + g) * kSlotWords;
+    return board + ((size_t)(epoch & 1u) * G + g) * kSlotStride;
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// Reads the five words of a slot with three agent-scope (sc1) vector loads
+// in flight at once; each aligned 64-bit word is read atomically.
+__device__ __forceinline__ void load_slot_agent(const unsigned long long *p, u32x4 &a, u32x4 &b, u32x2 &c)
+{
+    asm volatile(
+        "global_load_dwordx4 %0, %3, off sc1\n\t"
+        "global_load_dwordx4 %1, %3, off offset:16 sc1\n\t"
+        "global_load_dwordx2 %2, %3, off offset:32 sc1\n\t"
+        "s_waitcnt vmcnt(0)"
+        : "=&v"(a), "=&v"(b), "=&v"(c)
+        : "v"(p)
+        : "memory");
 }
 
 __device__ __forceinline__ void publish(unsigned long long *slot, uint32_t epoch, const Candidate &c)
@@ -190,18 +298,18 @@ __device__ __forceinline__ void publish(unsigned long long *slot, uint32_t epoch
 // epoch or when the spin budget runs out.
 __device__ __forceinline__ bool poll_slot(const unsigned long long *slot, uint32_t epoch, Candidate &c)
 {
+    // little-endian words: .x = payload (low half), .y = epoch (high half)
     for (uint32_t spin = 0; spin < kSpinLimit; ++spin) {
-        unsigned long long w0 = ld_agent(slot + 0), w1 = ld_agent(slot + 1), w2 = ld_agent(slot + 2),
-                           w3 = ld_agent(slot + 3), w4 = ld_agent(slot + 4);
-        uint32_t e0 = (uint32_t)(w0 >> 32);
-        if (e0 == kAbortEpoch || (uint32_t)(w1 >> 32) == kAbortEpoch)
+        u32x4 a, b;
+        u32x2 e;
+        load_slot_agent(slot, a, b, e);
+        if (a.y == kAbortEpoch || a.w == kAbortEpoch)
             return false;
-        if (e0 == epoch && (uint32_t)(w1 >> 32) == epoch && (uint32_t)(w2 >> 32) == epoch &&
-            (uint32_t)(w3 >> 32) == epoch && (uint32_t)(w4 >> 32) == epoch) {
-            c.key = ((w0 & 0xffffffffull) << 32) | (w1 & 0xffffffffull);
-            c.x = __uint_as_float((uint32_t)w2);
-            c.y = __uint_as_float((uint32_t)w3);
-            c.z = __uint_as_float((uint32_t)w4);
+        if (a.y == epoch && a.w == epoch && b.y == epoch && b.w == epoch && e.y == epoch) {
+            c.key = ((unsigned long long)a.x << 32) | a.z;
+            c.x = __uint_as_float(b.x);
+            c.y = __uint_as_float(b.z);
+            c.z = __uint_as_float(e.x);
             return true;
         }
     }
@@ -212,7 +320,7 @@ __device__ __forceinline__ void publish_abort(unsigned long long *board, int G, 
 {
     for (int par = 0; par < 2; ++par)
         for (int w = 0; w < kSlotWords; ++w)
-            st_agent(board + ((size_t)par * G + g) * kSlotWords + w, (unsigned long long)kAbortEpoch << 32);
+            st_agent(board + ((size_t)par * G + g) * kSlotStride + w, (unsigned long long)kAbortEpoch << 32);
 }
 
 // ---------------------------------------------------------------------------
@@ -225,12 +333,17 @@ hipError_t launch_scan(const uint32_t *in, uint32_t *out, int n, uint32_t *parti
 
 struct SampleLaunch {
     int G;
+    int R;                // lookahead depth of the multi-pick sampler; 0 = one selection per exchange
     uint32_t flags;
     uint32_t lds_budget;  // dynamic LDS bytes per workgroup
 };
-// Static LDS of the sampler kernel (bytes).
-size_t rfps_sampler_static_lds();
+// Static LDS of the sampler kernel chosen by R (bytes); 0 if R is not supported.
+size_t rfps_sampler_static_lds(int R);
 hipError_t launch_rfps_sample(const IndexView &v, int m, int start, const SampleLaunch &L, int32_t *out_idx,
+                              float *out_d2, hipStream_t s);
+// The multi-pick sampler (sample_rounds.hip); called by launch_rfps_sample.
+size_t rfps_rounds_static_lds(int R);
+hipError_t launch_rfps_rounds(const IndexView &v, int m, int start, const SampleLaunch &L, int32_t *out_idx,
                               float *out_d2, hipStream_t s);
 
 struct PlainLaunch {

@@ -33,7 +33,7 @@ __global__ void k_plain_reset(PlainArgs a)
             a.out_d2[0] = INFINITY;
     }
     if (a.board)
-        for (int w = tid; w < 2 * a.G * kSlotWords; w += gridDim.x * blockDim.x)
+        for (int w = tid; w < 2 * a.G * kSlotStride; w += gridDim.x * blockDim.x)
             a.board[w] = 0ull;
 }
 

@@ -21,37 +21,6 @@
 
 namespace rfps {
 
-// Pruning threshold of a tile with radius R (rounded up) and Dist_v = dv.
-//
-// Skipping the tile for sample s is safe when the FP32 value
-// q = fl32(||s - c||^2), computed with the same formula as a point distance,
-// satisfies q >= thr.  Derivation: q <= (1 + 2^-24)^5 ||s - c||^2, so
-// q >= thr implies ||s - c|| >= R + sqrt(dv / (1 - 2^-20)); by the triangle
-// inequality (eq. triangle_inequality_bound) every member p then has
-// ||p - s||^2 >= dv / (1 - 2^-20), and its FP32 squared distance, at least
-// (1 - 2^-24)^5 ||p - s||^2, is >= dv >= Dist_p[p]: the strict update cannot
-// fire (eq. radius_pruning_correctness).  The FP64 steps below are rounded
-// up by relative margins far above their rounding error.  dv == 0 means
-// nothing can decrease (thr = 0 always skips); dv below 2^-100 or above
-// 2^100 returns NaN, which never skips.
-__device__ __forceinline__ float prune_threshold(float R, float dv)
-{
-    if (dv == 0.0f)
-        return 0.0f;
-    if (!(dv >= 0x1p-100f) || !(dv <= 0x1p100f))
-        return __uint_as_float(0x7fc00000u);
-    double q = (double)R + sqrt((double)dv / (1.0 - 0x1p-20));
-    q *= 1.0 + 0x1p-50;
-    double T = q * q * (1.0 + 0x1p-50);
-    double t64 = T * (1.0 + 0x1p-20);
-    if (!(t64 <= 3.0e38))
-        return __uint_as_float(0x7fc00000u);
-    float thr = (float)t64;
-    if ((double)thr < t64)
-        thr = nextafterf(thr, INFINITY);
-    return thr;
-}
-
 struct SampleArgs {
     IndexHeader *hdr;
     const float *xs, *ys, *zs;
@@ -97,13 +66,14 @@ __global__ void k_sample_reset(IndexHeader *hdr, unsigned long long *board, int 
     if (tid == 0) {
         hdr->sample_status = 0;
         hdr->last_m = (uint32_t)m;
-        for (int t = 0; t < 8; ++t)
+        hdr->trace_n = 0;
+        for (int t = 0; t < kTeleFields; ++t)
             hdr->tele[t] = 0;
         out_idx[0] = start;
         if (out_d2)
             out_d2[0] = INFINITY;
     }
-    for (int w = tid; w < 2 * G * kSlotWords; w += gridDim.x * blockDim.x)
+    for (int w = tid; w < kBoardWords; w += gridDim.x * blockDim.x)
         board[w] = 0ull;
 }
 
@@ -393,16 +363,21 @@ __global__ __launch_bounds__(kBlock) void k_rfps(SampleArgs a)
         if (g == 0 && tid == 0) {
             atomicAdd(&hdr->tele[0], (unsigned long long)(a.m > 1 ? a.m - 2 : 0));
             atomicAdd(&hdr->tele[1], (unsigned long long)NT);
+            atomicAdd(&hdr->tele[8], (unsigned long long)(a.m > 1 ? a.m - 1 : 0));
         }
     }
+    if (g == 0 && tid == 0)
+        hdr->trace_n = (uint32_t)(a.m > 1 ? a.m - 1 : 0);
 }
 
 }  // namespace rfps
 
 namespace rfps {
 
-size_t rfps_sampler_static_lds()
+size_t rfps_sampler_static_lds(int R)
 {
+    if (R > 0)
+        return rfps_rounds_static_lds(R);
     hipFuncAttributes attr;
     if (hipFuncGetAttributes(&attr, reinterpret_cast<const void *>(k_rfps)) != hipSuccess)
         return 0;
@@ -413,43 +388,52 @@ hipError_t launch_rfps_sample(const IndexView &v, int m, int start, const Sample
                               float *out_d2, hipStream_t s)
 {
     k_sample_reset<<<4, kBlock, 0, s>>>(v.hdr, v.board, L.G, start, out_idx, out_d2, m);
-    k_rfps_plan<<<(L.G + kBlock - 1) / kBlock, kBlock, 0, s>>>(v.hdr, v.tcnt, L.G, L.lds_budget);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    if (m > 1) {
-        SampleArgs a;
-        a.hdr = v.hdr;
-        a.xs = v.xs;
-        a.ys = v.ys;
-        a.zs = v.zs;
-        a.orig = v.orig;
-        a.inv = v.inv;
-        a.tstart = v.tstart;
-        a.tcnt = v.tcnt;
-        a.tcx = v.tcx;
-        a.tcy = v.tcy;
-        a.tcz = v.tcz;
-        a.trad = v.trad;
-        a.board = v.board;
-        a.trace = v.trace;
-        a.out_idx = out_idx;
-        a.out_d2 = out_d2;
-        a.n = v.n;
-        a.m = m;
-        a.start = start;
-        a.G = L.G;
-        a.flags = L.flags;
-        a.lds_budget = L.lds_budget;
-        void *args[] = {&a};
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_rfps), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)L.lds_budget);
+    if (L.R > 0) {
+        e = launch_rfps_rounds(v, m, start, L, out_idx, out_d2, s);
         if (e != hipSuccess)
             return e;
-        e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_rfps), dim3(L.G), dim3(kBlock), args,
-                                       L.lds_budget, s);
+    } else {
+        k_rfps_plan<<<(L.G + kBlock - 1) / kBlock, kBlock, 0, s>>>(v.hdr, v.tcnt, L.G, L.lds_budget);
+        e = hipGetLastError();
         if (e != hipSuccess)
             return e;
+        if (m > 1) {
+            SampleArgs a;
+            a.hdr = v.hdr;
+            a.xs = v.xs;
+            a.ys = v.ys;
+            a.zs = v.zs;
+            a.orig = v.orig;
+            a.inv = v.inv;
+            a.tstart = v.tstart;
+            a.tcnt = v.tcnt;
+            a.tcx = v.tcx;
+            a.tcy = v.tcy;
+            a.tcz = v.tcz;
+            a.trad = v.trad;
+            a.board = v.board;
+            a.trace = v.trace;
+            a.out_idx = out_idx;
+            a.out_d2 = out_d2;
+            a.n = v.n;
+            a.m = m;
+            a.start = start;
+            a.G = L.G;
+            a.flags = L.flags;
+            a.lds_budget = L.lds_budget;
+            void *args[] = {&a};
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_rfps),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_budget);
+            if (e != hipSuccess)
+                return e;
+            e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_rfps), dim3(L.G), dim3(kBlock), args,
+                                           L.lds_budget, s);
+            if (e != hipSuccess)
+                return e;
+        }
     }
     k_sample_finalize<<<(m + kBlock - 1) / kBlock, kBlock, 0, s>>>(v.hdr, m, out_idx, out_d2);
     return hipGetLastError();

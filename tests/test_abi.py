@@ -40,14 +40,18 @@ def test_status_strings(L):
 
 def test_workspace_sizes(L):
     import paper_2606_06255_amd as rf
-    p = rf.rfps_params(16, 0, 0, 0)
+    p = rf.rfps_params(n_vox=16)
     a = L.rfps_index_workspace_size(1000, ctypes.byref(p))
     b = L.rfps_index_workspace_size(100000, ctypes.byref(p))
     assert 0 < a < b and a % 256 == 0
     assert L.rfps_index_workspace_size(0, ctypes.byref(p)) == 0
     assert L.rfps_index_workspace_size(-5, None) == 0
-    for bad in (rf.rfps_params(2000, 0, 0, 0), rf.rfps_params(16, 65, 0, 0), rf.rfps_params(16, 0, 257, 0),
-                rf.rfps_params(16, 0, 0, 0x100), rf.rfps_params(-1, 0, 0, 0)):
+    for la in (2, 4, 8):
+        ok = rf.rfps_params(n_vox=16, lookahead=la)
+        assert L.rfps_index_workspace_size(1000, ctypes.byref(ok)) == a
+    for bad in (rf.rfps_params(n_vox=2000), rf.rfps_params(n_vox=16, tile=65), rf.rfps_params(groups=257),
+                rf.rfps_params(flags=0x100), rf.rfps_params(n_vox=-1), rf.rfps_params(lookahead=3),
+                rf.rfps_params(lookahead=16), rf.rfps_params(lookahead=-1)):
         assert L.rfps_index_workspace_size(1000, ctypes.byref(bad)) == 0
     assert L.rfps_fps_plain_workspace_size(1000, 0) > 0
     assert L.rfps_fps_plain_workspace_size(1000, 2) == 0

@@ -59,16 +59,19 @@ def test_rfps_cube_partitions(oracle_lib):
     for n_vox in (1, 4, 8, 16, 32):
         for tile in (0, 1, 7):
             idx = m.build_index(x, n_vox=n_vox, tile=tile)
-            nt = m.read_index_info(idx)["n_tiles"]
             for g in (1, 3, 64, 0):
-                got = m.sample(idx, 1024, 0, groups=g)
-                st = m.read_status(idx)
-                if g == 1 and nt * 40 + P.shape[0] * 20 > 160 * 1024:
-                    # one workgroup cannot hold 4096 one-point tiles: a clean capacity error
-                    assert st == 6 and np.all(host(got[0]) == -1)
-                    continue
-                assert st == 0, (n_vox, tile, g, st)
-                assert_same(got, ref, "n_vox=%d tile=%d g=%d" % (n_vox, tile, g))
+                for la, fl in ((0, 0), (2, 0), (8, 0), (0, m.F_SINGLE_PICK)):
+                    got = m.sample(idx, 1024, 0, groups=g, lookahead=la, flags=fl)
+                    st = m.read_status(idx)
+                    what = "n_vox=%d tile=%d g=%d lookahead=%d flags=%d" % (n_vox, tile, g, la, fl)
+                    if st == 6:
+                        # only a single workgroup can run out of LDS on 4096 points;
+                        # the error is clean: every output is poisoned
+                        assert g == 1, what
+                        assert np.all(host(got[0]) == -1)
+                        continue
+                    assert st == 0, (what, st)
+                    assert_same(got, ref, what)
 
 
 def test_rfps_flags_cube(oracle_lib):
@@ -77,7 +80,7 @@ def test_rfps_flags_cube(oracle_lib):
     ref = oracle_lib.fps(P, 1024, 5)
     idx = m.build_index(dev(P), n_vox=8)
     for flags in (m.F_NO_PRUNE, m.F_NO_POINT_SKIP, m.F_TELEMETRY, m.F_TRACE,
-                  m.F_NO_PRUNE | m.F_NO_POINT_SKIP):
+                  m.F_NO_PRUNE | m.F_NO_POINT_SKIP, m.F_SINGLE_PICK, m.F_SINGLE_PICK | m.F_NO_POINT_SKIP):
         assert_same(m.sample(idx, 1024, 5, flags=flags), ref, "flags=%d" % flags)
 
 
@@ -101,6 +104,9 @@ def test_room_full(oracle_lib):
     x = dev(P)
     assert_same(m.fps(x, 20000, 0), ref, "rfps default")
     assert_same(m.fps(x, 20000, 0, n_vox=48, tile=32, groups=128), ref, "rfps n48 t32 g128")
+    assert_same(m.fps(x, 20000, 0, groups=32, lookahead=8), ref, "rfps g32 lookahead 8")
+    assert_same(m.fps(x, 20000, 0, groups=256, lookahead=2), ref, "rfps g256 lookahead 2")
+    assert_same(m.fps(x, 20000, 0, flags=m.F_SINGLE_PICK), ref, "rfps single pick")
     assert_same(m.fps_plain(x, 20000, 0, variant=0), ref, "plain persistent")
 
 
@@ -138,6 +144,8 @@ def test_edge_cases(oracle_lib):
         x = dev(P)
         for n_vox in (1, 8, 64):
             assert_same(m.fps(x, mm, s, n_vox=n_vox), ref, "%s n_vox=%d" % (name, n_vox))
+        assert_same(m.fps(x, mm, s, groups=7, lookahead=2), ref, name + " g7 la2")
+        assert_same(m.fps(x, mm, s, flags=m.F_SINGLE_PICK), ref, name + " single")
         assert_same(m.fps_plain(x, mm, s, variant=0), ref, name + " plain0")
         assert_same(m.fps_plain(x, mm, s, variant=1), ref, name + " plain1")
 
@@ -190,23 +198,38 @@ def test_telemetry_sane(oracle_lib):
     m = rf()
     P = synth.room(2)[:20000]
     idx = m.build_index(dev(P), n_vox=24)
-    m.sample(idx, 5000, 0, flags=m.F_TELEMETRY)
-    t = m.read_telemetry(idx)
     info = m.read_index_info(idx)
-    assert t["iters"] == 4998 and t["tiles"] == info["n_tiles"]
-    assert t["tile_tests"] == t["iters"] * t["tiles"]
-    assert 0 < t["tiles_pruned"] < t["tile_tests"]
-    assert t["points_visited"] == t["points_skipped"] + (t["points_visited"] - t["points_skipped"])
-    assert t["points_updated"] <= t["points_visited"] - t["points_skipped"]
     # strict decreases are a property of the sequence, not of the partition
     _, _, cpu = oracle_lib.rfps_cpu(P, 5000, 0, n_vox=24)
-    assert t["points_updated"] == cpu["points_updated"]
+    for fl in (m.F_TELEMETRY | m.F_SINGLE_PICK, m.F_TELEMETRY):
+        m.sample(idx, 5000, 0, flags=fl)
+        t = m.read_telemetry(idx)
+        assert t["iters"] == 4998 and t["tiles"] == info["n_tiles"]
+        assert 0 < t["tiles_pruned"] < t["tile_tests"]
+        assert t["points_updated"] <= t["points_visited"] - t["points_skipped"]
+        if fl & m.F_SINGLE_PICK:
+            assert t["tile_tests"] == t["iters"] * t["tiles"]
+            assert t["exchanges"] == 4999
+            # one strict decrease per (point, selection), as in plain FPS
+            assert t["points_updated"] == cpu["points_updated"]
+        else:
+            assert 0 < t["exchanges"] < 4999
+            # a round applies all its selections at once: a point lowered by
+            # several of them is stored (and counted) once
+            assert 0 < t["points_updated"] <= cpu["points_updated"]
+            assert t["tick_hz"] > 0 and t["ticks_merge"] > 0 and t["ticks_exchange"] > 0
 
 
-def test_trace_records_every_selection():
+def test_trace_records_every_exchange():
     m = rf()
     idx = m.build_index(dev(synth.cube(0)))
-    m.sample(idx, 1024, 0, flags=m.F_TRACE)
+    m.sample(idx, 1024, 0, flags=m.F_TRACE | m.F_SINGLE_PICK)
     tr, hz = m.read_trace(idx)
     assert tr.shape == (1023, 2) and hz > 0
     assert np.all(tr[:, 1] >= tr[:, 0])
+    m.sample(idx, 1024, 0, flags=m.F_TRACE)
+    tr, hz = m.read_trace(idx)
+    picks = (tr[:, 1] >> np.uint64(48)).astype(np.int64)
+    assert picks.sum() == 1023 and np.all(picks >= 1)
+    t1 = tr[:, 1] & np.uint64((1 << 48) - 1)
+    assert np.all(t1 >= tr[:, 0])
