@@ -9,7 +9,7 @@
  * same precision, arg max returns the smallest original index among equal
  * distances).
  *
- * Reading of the paper used here (all listed in the design notes):
+ * Reading of the paper used here:
  *   - the distance state and every reported distance is the FP32 *squared*
  *     Euclidean distance, evaluated as ((dx*dx + dy*dy) + dz*dz) with
  *     dx = fl(p_x - s_x) and no fused multiply-add (build with
