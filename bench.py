@@ -7,6 +7,12 @@ One step = the whole path on one cloud already resident in HBM: voxel
 parameter choice, index build (bounding box, voxel ids, radix sort, gather,
 compaction, tiles and spheres) and the persistent sampler (all M selections).
 
+With --workload batch one step is one batched call (index build and
+sampling of 32 uneven clouds in one persistent launch, parameters from the
+library's autotuner, picked during warm-up), replayed from a captured HIP
+graph; per-cloud launches of the single-cloud path, the batched call
+without the graph and per-cloud plain FPS are timed beside it.
+
 Prints one JSON line (rank 0).  `value` is selected points per second over
 the timed steps; `ms_per_step` is the ms per cloud.  Beside it: the plain GPU
 FPS comparators on the same cloud and GPU, the roofline of the sampler kernel
@@ -32,6 +38,8 @@ WORKLOADS = {
     "room": "indoor room-like cloud, N=80,000, M=20,000",
     "lidar": "spinning LiDAR-like cloud, 64 beams x 1800 azimuth minus 576 drops, N=114,624, M=28,656",
     "cube": "uniform unit cube, N=4096, M=1024",
+    "batch": "32 uneven clouds in one call, N_i log-uniform in [8000, 120000], even i room-like, odd i "
+             "LiDAR-like, M_i = N_i // 4, int32 CSR offsets",
 }
 
 
@@ -85,12 +93,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparators", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=256, help="size of the copy kernel used to calibrate counters")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU time budget of the oracle baseline")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(clouds would shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: there is no multi-GPU path (batched clouds would shard "
+              "across GPUs by cost with no exchange; a single cloud needs one exchange per round)",
+              file=sys.stderr)
         return 2
 
     import numpy as np
@@ -104,6 +114,11 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
+
+    if args.workload == "batch":
+        result = run_batch(args, rf, dev, stream)
+        print(json.dumps(result), flush=True)
+        return 0
 
     P, M = load_workload(args.workload)
     N = P.shape[0]
@@ -167,7 +182,7 @@ def main():
     ex_us = (t_done - tr[:, 0].astype(np.int64)).astype(np.float64) / hz * 1e6
     it_us = np.diff(t_done) / hz * 1e6 if len(t_done) > 1 else np.zeros(1)
     NT = info["n_tiles"]
-    # algorithmic bytes of one sampler launch (see the design notes):
+    # algorithmic bytes of one sampler launch:
     #   prologue: 16 B per point (x, y, z, original index) + 20 B per tile (sphere, count)
     #   per update round: 24 B per tile (sphere test 16 B + key scan 8 B),
     #     16 B per visited point (x, y, z, D), 4 B per updated D, 12 B per resynced tile
@@ -272,28 +287,197 @@ def main():
 
     # ---- CPU baseline: the oracle on the host cores, bounded prefix ---------
     if not args.no_cpu_baseline:
-        import oracle
-        oracle.build(force=False)
-        threads = oracle.num_threads()
-        mp = min(M, 512)
-        t0 = time.perf_counter()
-        oracle.fps(P, mp, 0, threads=0)
-        t1 = time.perf_counter()
-        per_sel = (t1 - t0) / max(1, mp - 1)
-        mp = int(min(M, max(mp, 1.5 / max(per_sel, 1e-9))))
-        t0 = time.perf_counter()
-        ri, rd = oracle.fps(P, mp, 0, threads=0)
-        t1 = time.perf_counter()
-        result["cpu_baseline"] = {
-            "value": (mp - 1) / (t1 - t0), "unit": "selected pts/s", "cores": threads, "kind": "oracle",
-            "sample": "first %d of the %d selections of the same cloud, plain O(N*M) FPS in C, OpenMP" % (mp, M),
-            "seconds": t1 - t0,
-            "bitexact_prefix": bool(np.array_equal(ri, got_i[:mp]) and np.array_equal(
-                rd.view(np.uint32), got_d[:mp].view(np.uint32))),
-        }
+        result["cpu_baseline"] = cpu_baseline([P], [M], [got_i], [got_d], args.cpu_seconds)
 
     print(json.dumps(result), flush=True)
     return 0
+
+
+def cpu_baseline(clouds, ms, gpu_idx, gpu_d2, seconds):
+    """The oracle (plain O(N*M) FPS in C, OpenMP over the host cores) on a
+    bounded prefix of every cloud's selections, about `seconds` of CPU time in
+    all; the prefixes are also checked against the GPU's outputs."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    threads = oracle.num_threads()
+    # probe the cost of one selection per point on the first cloud
+    mp0 = min(ms[0], 64)
+    t0 = time.perf_counter()
+    oracle.fps(clouds[0], mp0, 0, threads=0)
+    per_pt_sel = (time.perf_counter() - t0) / max(1, (mp0 - 1) * clouds[0].shape[0])
+    work = sum(c.shape[0] * (m - 1) for c, m in zip(clouds, ms))
+    frac = min(1.0, seconds / max(per_pt_sel * work, 1e-9))
+    sel, same = 0, True
+    t0 = time.perf_counter()
+    for c, m, gi, gd in zip(clouds, ms, gpu_idx, gpu_d2):
+        mp = max(2, min(m, int(round(frac * m))))
+        ri, rd = oracle.fps(c, mp, 0, threads=0)
+        sel += mp - 1
+        same &= bool(np.array_equal(ri, gi[:mp]) and np.array_equal(rd.view(np.uint32), gd[:mp].view(np.uint32)))
+    dt = time.perf_counter() - t0
+    total = sum(m for m in ms)
+    return {"value": sel / dt, "unit": "selected pts/s", "cores": threads, "kind": "oracle",
+            "sample": "first %.1f%% of the selections of every cloud of the same workload (%d of %d selections, "
+                      "%d cloud%s), plain O(N*M) FPS in C, OpenMP" % (100 * frac, sel, total - len(ms), len(ms),
+                                                                      "s" if len(ms) > 1 else ""),
+            "seconds": dt, "bitexact_prefix": same}
+
+
+def run_batch(args, rf, dev, stream):
+    """The batched workload: 32 uneven clouds, one call per step."""
+    import numpy as np
+    import torch
+    import synth
+
+    xyz, offsets, m = synth.batch(0, b=32)
+    B, N, MT = len(m), xyz.shape[0], int(m.sum())
+    sizes = np.diff(offsets)
+    x = torch.from_numpy(xyz).to(dev)
+    off_d = torch.from_numpy(offsets).to(dev)
+    m_d = torch.from_numpy(m).to(dev)
+    ws = rf.BatchWorkspace(N, B, dev)
+    out_i = torch.empty(MT, dtype=torch.int32, device=dev)
+    out_d = torch.empty(MT, dtype=torch.float32, device=dev)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    # parameters from the autotuner (untimed; part of the warm-up)
+    t0 = time.perf_counter()
+    chosen, tuned_ms, _ = rf.autotune_batched(x, offsets, m, reps=3, ws=ws)
+    tune_s = time.perf_counter() - t0
+    log("autotuner: %s, %.2f ms per batch (%.1f s)" % (chosen, tuned_ms, tune_s))
+    kw = dict(groups=chosen["groups"], lookahead=chosen["lookahead"], tile=chosen["tile"])
+
+    def call(flags=0, **over):
+        p = dict(kw)
+        p.update(over)
+        rf.sample_batched(x, off_d, m_d, m_total=MT, ws=ws, out_idx=out_i, out_d2=out_d, check=False,
+                          flags=flags, **p)
+
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        call()
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        call()
+
+    # ---- timed region: graph replays ----------------------------------------
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    st = rf.batched_read_status(ws)
+    if st != 0:
+        raise rf.RfpsError(st, "device status")
+    a, b = ev(), ev()
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    a.record(stream)
+    for _ in range(args.steps):
+        graph.replay()
+    b.record(stream)
+    torch.cuda.synchronize()
+    wall1 = time.perf_counter()
+    ms_per_step = a.elapsed_time(b) / args.steps
+    st = rf.batched_read_status(ws)
+    if st != 0:
+        raise rf.RfpsError(st, "device status")
+    got_i = out_i.cpu().numpy().copy()
+    got_d = out_d.cpu().numpy().copy()
+    log("timed %d graph replays: %.3f ms/batch (wall %.3f ms)" % (args.steps, ms_per_step,
+                                                                  1e3 * (wall1 - wall0) / args.steps))
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    reps = max(1, min(args.steps, 5))
+    eager_ms = timed(call, reps)
+    default_ms = timed(lambda: call(groups=0, lookahead=0, tile=0), reps)
+    same_default = np.array_equal(out_i.cpu().numpy(), got_i)
+
+    # telemetry of the tuned call (roofline of the whole call)
+    call(flags=rf.F_TELEMETRY)
+    tel = rf.batched_read_telemetry(ws)
+    NT = tel["tiles"]
+    # as for one cloud, with the sphere tests counted by the sampler (every
+    # tile of a cloud against every selection of that cloud)
+    alg_bytes = (16 * N + 20 * NT + 24 * tel["tile_tests"] + 16 * tel["points_visited"]
+                 + 4 * tel["points_updated"] + 12 * tel["tiles_resynced"] + 8 * (MT - B))
+    achieved = alg_bytes / (ms_per_step / 1e3) / 1e9
+    visit = tel["points_visited"] / max(1, int((sizes.astype(np.int64) * (m.astype(np.int64) - 1)).sum()))
+
+    # ---- comparators: per-cloud launches of the single-cloud path -------------
+    comps = {}
+    o = np.concatenate([[0], np.cumsum(m)])
+    per_i = torch.empty(MT, dtype=torch.int32, device=dev)
+    per_d = torch.empty(MT, dtype=torch.float32, device=dev)
+    order = np.argsort(-sizes, kind="stable")
+    idx = rf.build_index(x[offsets[order[0]]:offsets[order[0] + 1]])
+
+    def per_cloud():
+        nonlocal idx
+        for c in range(B):
+            idx = rf.build_index(x[offsets[c]:offsets[c + 1]], reuse=idx)
+            rf.sample(idx, int(m[c]), 0, out_idx=per_i[o[c]:o[c + 1]], out_d2=per_d[o[c]:o[c + 1]])
+
+    comps["per_cloud_rfps_ms"] = timed(per_cloud, 2)
+    same_per = np.array_equal(per_i.cpu().numpy(), got_i) and np.array_equal(
+        per_d.cpu().numpy().view(np.uint32), got_d.view(np.uint32))
+    pws = rf.PlainWorkspace(int(sizes.max()), dev)
+
+    def per_cloud_plain():
+        for c in range(B):
+            rf.fps_plain(x[offsets[c]:offsets[c + 1]], int(m[c]), 0, variant=0, ws=pws,
+                         out_idx=per_i[o[c]:o[c + 1]], out_d2=per_d[o[c]:o[c + 1]], check=False)
+
+    comps["per_cloud_plain_persistent_ms"] = timed(per_cloud_plain, 1)
+    same_plain = np.array_equal(per_i.cpu().numpy(), got_i)
+    comps["batched_eager_tuned_ms"] = eager_ms
+    comps["batched_eager_default_ms"] = default_ms
+
+    result = {
+        "metric": METRIC,
+        "value": MT / (ms_per_step / 1e3),
+        "unit": "selected pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batch", "description": WORKLOADS["batch"], "clouds": B, "n_points": N,
+                   "m_total": MT, "n_min": int(sizes.min()), "n_max": int(sizes.max()), "start": 0,
+                   "n_vox": "per-cloud default", "tuned": chosen, "launch": "hipGraph replay"},
+        "ms_per_cloud": ms_per_step / B,
+        "autotune": {"chosen": chosen, "median_ms": tuned_ms, "seconds": tune_s},
+        "pruning": {"point_visit_fraction": visit, **tel},
+        "roofline": {"bound": "hbm", "kernel": "whole batched call (index build + k_rfps_rounds_batched)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "alg_bytes_per_launch": alg_bytes},
+        "comparators": comps,
+        "speedup_vs_per_cloud_rfps": comps["per_cloud_rfps_ms"] / ms_per_step,
+        "speedup_vs_per_cloud_plain_persistent": comps["per_cloud_plain_persistent_ms"] / ms_per_step,
+        "graph_vs_eager": eager_ms / ms_per_step,
+        "bitexact_vs_per_cloud": bool(same_per and same_plain and same_default),
+    }
+    if not args.no_cpu_baseline:
+        clouds = [xyz[offsets[c]:offsets[c + 1]] for c in range(B)]
+        result["cpu_baseline"] = cpu_baseline(clouds, [int(v) for v in m], [got_i[o[c]:o[c + 1]] for c in range(B)],
+                                              [got_d[o[c]:o[c + 1]] for c in range(B)], args.cpu_seconds)
+    return result
 
 
 if __name__ == "__main__":

@@ -76,6 +76,13 @@ typedef struct rfps_params {
     int32_t lookahead;
     /* RFPS_F_* bits. */
     uint32_t flags;
+    /* Range shells (an extension; output-neutral like every partition):
+     * 0 or +inf = one shell, the uniform grid of Sec. 3.2.  A spacing
+     * Delta > 0 splits the cloud into shells of width Delta around its
+     * bounding-box centre; shell s (distance in [s, s+1) * Delta, the last
+     * one open-ended, at most 64) uses cubes of edge (s+1) * L, so sparse
+     * far-range points of a spinning sensor share fewer, fuller voxels. */
+    float shell_spacing;
 } rfps_params;
 
 /* Handle to a voxel index built by rfps_build_index().  Plain data: it
@@ -84,7 +91,7 @@ typedef struct rfps_index {
     int32_t n;        /* points */
     int32_t n_vox;    /* resolved voxel bins per axis */
     int32_t tile;     /* resolved tile size */
-    int32_t reserved;
+    int32_t shells;   /* range shells the grid may use (1 = none) */
     void *ws;         /* device workspace holding the index */
     size_t ws_bytes;
 } rfps_index;
@@ -206,6 +213,75 @@ rfps_status rfps_fps_plain(const float *xyz, int32_t n, int32_t m, int32_t start
 /* Waits for the stream, then returns the device-side status recorded in a
  * plain-FPS workspace by the last rfps_fps_plain() call on it. */
 rfps_status rfps_read_plain_status(const void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Batches of clouds.  The exact FPS of Algorithm 1 (Sec. 2.1, with the
+ * Sec. 3.1 tie rule) runs independently on every cloud of a batch; one call
+ * builds one spherical-voxel index over all clouds (Sec. 3.2, every cloud on
+ * its own grid) and samples all of them in one persistent launch.  Teams of
+ * `groups` workgroups, each team on one XCD, take the clouds from a queue
+ * ordered by decreasing N_c * m_c.  Output-neutral like the single-cloud
+ * parameters: the selections of every cloud equal plain FPS on that cloud.
+ *   xyz       device, float32 [n][3]: the clouds one after the other.
+ *   n         total points, 1 <= n <= 2^26.
+ *   offsets   device, int32 [batch + 1]: cloud c is points offsets[c] ..
+ *             offsets[c+1]-1; offsets[0] = 0, offsets[batch] = n, and every
+ *             cloud has at least one point.
+ *   m         device, int32 [batch]: selections of cloud c, 1 <= m[c] <= N_c.
+ *   starts    device, int32 [batch] or NULL: local index of the first sample
+ *             of cloud c, 0 <= starts[c] < N_c (NULL: all 0).
+ *   batch     clouds, 1 <= batch <= min(4096, n).
+ *   m_total   sum of m[c]: the length of the outputs (checked on the device).
+ *   params    host, may be NULL.  n_vox: 0 = per-cloud default bins, else
+ *             the same bins for every cloud; tile as for rfps_build_index;
+ *             groups: workgroups per cloud (a divisor of the compute units of
+ *             one XCD, at least 2; 0 = all of them); lookahead 2, 4 or 8 (0 =
+ *             4).  RFPS_F_NO_PRUNE, RFPS_F_SINGLE_PICK and RFPS_F_TRACE are
+ *             not available here (RFPS_ERR_UNSUPPORTED).
+ *   ws        device workspace of rfps_batched_workspace_size() bytes,
+ *             256-byte aligned; calls on one workspace must not overlap.
+ *   out_idx   device, int32 [m_total]: the selections of cloud c at
+ *             m[0] + .. + m[c-1] onwards, as indices local to the cloud.
+ *   out_d2    device, float32 [m_total] or NULL: squared distances as for
+ *             rfps_sample, per cloud (each cloud's first entry is +inf).
+ * The call allocates nothing and never waits for the device, so it may be
+ * captured into a HIP graph (under capture the persistent kernel is an
+ * ordinary launch after a residency check).  Device-side errors (offsets,
+ * m, starts or m_total inconsistent, non-finite input, capacity) are
+ * recorded in the workspace; all outputs then become -1 / NaN.
+ */
+size_t rfps_batched_workspace_size(int32_t n, int32_t batch, const rfps_params *params);
+rfps_status rfps_sample_batched(const float *xyz, int32_t n, const int32_t *offsets,
+                                const int32_t *m, const int32_t *starts, int32_t batch,
+                                int32_t m_total, const rfps_params *params, void *ws,
+                                size_t ws_bytes, int32_t *out_idx, float *out_d2, void *stream);
+
+/* Waits for the stream and returns the device-side status the last batched
+ * call recorded in ws (RFPS_OK if none). */
+rfps_status rfps_batched_read_status(const void *ws, size_t ws_bytes, void *stream);
+
+/* Waits for the stream and copies the counters of the last batched call made
+ * with RFPS_F_TELEMETRY (summed over all clouds; the phase clocks stay 0). */
+rfps_status rfps_batched_read_telemetry(const void *ws, size_t ws_bytes, void *stream,
+                                        rfps_telemetry *out);
+
+/*
+ * Autotuner for batched calls: times rfps_sample_batched on this batch for
+ * every combination of groups (per_xcd, per_xcd/2, .. down to 4), lookahead
+ * (2, 4, 8) and tile (32, 64) that `base` leaves at 0 (non-zero fields of
+ * base are kept), `reps` timed runs each after one untimed run, and returns
+ * the fastest by median in *best (host) and its median in *best_ms (host,
+ * may be NULL).  Shapes the device cannot hold (RFPS_ERR_CAPACITY,
+ * RFPS_ERR_UNSUPPORTED) are skipped; every other candidate must reproduce
+ * the first one's selections exactly (else RFPS_ERR_INTERNAL).  On return
+ * the outputs hold the result of the chosen configuration.  Synchronous:
+ * it waits for the device and is not for use under graph capture.
+ */
+rfps_status rfps_autotune_batched(const float *xyz, int32_t n, const int32_t *offsets,
+                                  const int32_t *m, const int32_t *starts, int32_t batch,
+                                  int32_t m_total, const rfps_params *base, int32_t reps,
+                                  void *ws, size_t ws_bytes, int32_t *out_idx, float *out_d2,
+                                  void *stream, rfps_params *best, float *best_ms);
 
 /* Static description of a status code. */
 const char *rfps_status_str(rfps_status s);

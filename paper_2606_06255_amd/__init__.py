@@ -32,12 +32,12 @@ WS_ALIGN = 256
 
 class rfps_params(ctypes.Structure):
     _fields_ = [("n_vox", ctypes.c_int32), ("tile", ctypes.c_int32), ("groups", ctypes.c_int32),
-                ("lookahead", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("lookahead", ctypes.c_int32), ("flags", ctypes.c_uint32), ("shell_spacing", ctypes.c_float)]
 
 
 class rfps_index(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_vox", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t)]
+                ("shells", ctypes.c_int32), ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t)]
 
 
 class rfps_telemetry(ctypes.Structure):
@@ -93,6 +93,38 @@ def lib() -> ctypes.CDLL:
         L.rfps_fps_plain.restype = ctypes.c_int
         L.rfps_read_plain_status.argtypes = [vp, sz, vp]
         L.rfps_read_plain_status.restype = ctypes.c_int
+        L.rfps_batched_workspace_size.argtypes = [i32, i32, P(rfps_params)]
+        L.rfps_batched_workspace_size.restype = sz
+        L.rfps_sample_batched.argtypes = [vp, i32, vp, vp, vp, i32, i32, P(rfps_params), vp, sz, vp, vp, vp]
+        L.rfps_sample_batched.restype = ctypes.c_int
+        L.rfps_batched_read_status.argtypes = [vp, sz, vp]
+        L.rfps_batched_read_status.restype = ctypes.c_int
+        L.rfps_batched_read_telemetry.argtypes = [vp, sz, vp, P(rfps_telemetry)]
+        L.rfps_batched_read_telemetry.restype = ctypes.c_int
+        L.rfps_autotune_batched.argtypes = [vp, i32, vp, vp, vp, i32, i32, P(rfps_params), i32, vp, sz, vp, vp,
+                                            vp, P(rfps_params), P(ctypes.c_float)]
+        L.rfps_autotune_batched.restype = ctypes.c_int
+        f32 = ctypes.c_float
+        L.rfps_mlp_candidate.argtypes = [i32, P(i32), P(f32)]
+        L.rfps_mlp_candidate.restype = i32
+        L.rfps_mlp_state_size.argtypes = []
+        L.rfps_mlp_state_size.restype = sz
+        L.rfps_mlp_workspace_size.argtypes = [i32]
+        L.rfps_mlp_workspace_size.restype = sz
+        L.rfps_mlp_load.argtypes = [vp, sz, vp, vp]
+        L.rfps_mlp_load.restype = ctypes.c_int
+        L.rfps_mlp_save.argtypes = [vp, sz, vp, vp]
+        L.rfps_mlp_save.restype = ctypes.c_int
+        L.rfps_mlp_features.argtypes = [vp, i32, vp, sz, vp, vp]
+        L.rfps_mlp_features.restype = ctypes.c_int
+        L.rfps_mlp_forward.argtypes = [vp, sz, vp, i32, vp, sz, vp, vp]
+        L.rfps_mlp_forward.restype = ctypes.c_int
+        L.rfps_mlp_gradient.argtypes = [vp, sz, vp, vp, vp, i32, vp, sz, vp, vp, vp]
+        L.rfps_mlp_gradient.restype = ctypes.c_int
+        L.rfps_mlp_train_step.argtypes = [vp, sz, vp, vp, vp, i32, f32, vp, sz, vp, vp]
+        L.rfps_mlp_train_step.restype = ctypes.c_int
+        L.rfps_mlp_choose.argtypes = [vp, sz, vp, i32, f32, vp, sz, vp, vp, vp]
+        L.rfps_mlp_choose.restype = ctypes.c_int
         L.rfps_status_str.argtypes = [ctypes.c_int]
         L.rfps_status_str.restype = ctypes.c_char_p
         L.rfps_default_n_vox.argtypes = [i32]
@@ -124,8 +156,8 @@ def _check_xyz(xyz: torch.Tensor):
         raise ValueError("xyz must be a contiguous float32 CUDA tensor of shape [N, 3]")
 
 
-def _params(n_vox=0, tile=0, groups=0, flags=0, lookahead=0) -> rfps_params:
-    return rfps_params(int(n_vox), int(tile), int(groups), int(lookahead), int(flags))
+def _params(n_vox=0, tile=0, groups=0, flags=0, lookahead=0, shell=0.0) -> rfps_params:
+    return rfps_params(int(n_vox), int(tile), int(groups), int(lookahead), int(flags), float(shell))
 
 
 def default_n_vox(n: int) -> int:
@@ -149,12 +181,13 @@ class Index:
         return int(self.handle.n_vox)
 
 
-def index_workspace_size(n: int, n_vox: int = 0, tile: int = 0) -> int:
-    p = _params(n_vox, tile)
+def index_workspace_size(n: int, n_vox: int = 0, tile: int = 0, shell: float = 0.0) -> int:
+    p = _params(n_vox, tile, shell=shell)
     return int(lib().rfps_index_workspace_size(int(n), ctypes.byref(p)))
 
 
-def build_index(xyz: torch.Tensor, n_vox: int = 0, tile: int = 0, reuse: Index | None = None) -> Index:
+def build_index(xyz: torch.Tensor, n_vox: int = 0, tile: int = 0, reuse: Index | None = None,
+                shell: float = 0.0) -> Index:
     """rfps_build_index on torch's current stream.
 
     With `reuse`, the workspace of that index is rebuilt in place when it is
@@ -163,7 +196,7 @@ def build_index(xyz: torch.Tensor, n_vox: int = 0, tile: int = 0, reuse: Index |
     _check_xyz(xyz)
     L = lib()
     n = xyz.shape[0]
-    p = _params(n_vox, tile)
+    p = _params(n_vox, tile, shell=shell)
     nbytes = L.rfps_index_workspace_size(n, ctypes.byref(p))
     if nbytes == 0:
         raise RfpsError(1, "rfps_index_workspace_size")
@@ -225,9 +258,9 @@ def read_trace(index: Index, cap: int = 1 << 17):
 
 
 def fps(xyz: torch.Tensor, m: int, start: int = 0, n_vox: int = 0, tile: int = 0, groups: int = 0,
-        flags: int = 0, lookahead: int = 0):
+        flags: int = 0, lookahead: int = 0, shell: float = 0.0):
     """Build the index and sample: exact FPS with spherical-voxel pruning."""
-    idx = build_index(xyz, n_vox=n_vox, tile=tile)
+    idx = build_index(xyz, n_vox=n_vox, tile=tile, shell=shell)
     out = sample(idx, m, start, groups=groups, flags=flags, lookahead=lookahead)
     st = read_status(idx)
     _check(st, "device status")
@@ -261,3 +294,207 @@ def fps_plain(xyz: torch.Tensor, m: int, start: int = 0, variant: int = 0, group
     if check:
         _check(lib().rfps_read_plain_status(ws.ptr, ws.nbytes, _stream(dev)), "device status")
     return out_idx, out_d2
+
+
+# ---------------------------------------------------------------------------
+# Batches of clouds
+# ---------------------------------------------------------------------------
+class BatchWorkspace:
+    """Device workspace of rfps_sample_batched for up to n points in `batch` clouds."""
+
+    def __init__(self, n: int, batch: int, device, n_vox: int = 0, shell: float = 0.0):
+        p = _params(n_vox, shell=shell)
+        self.nbytes = int(lib().rfps_batched_workspace_size(int(n), int(batch), ctypes.byref(p)))
+        if self.nbytes == 0:
+            raise RfpsError(1, "rfps_batched_workspace_size")
+        self.buf, self.ptr = _workspace(self.nbytes, device)
+        self.device = device
+        self.n, self.batch, self.n_vox = int(n), int(batch), int(n_vox)
+
+    def fits(self, n: int, batch: int, n_vox: int, shell: float = 0.0) -> bool:
+        p = _params(n_vox, shell=shell)
+        need = int(lib().rfps_batched_workspace_size(int(n), int(batch), ctypes.byref(p)))
+        return 0 < need <= self.nbytes
+
+
+def _i32_dev(x, device) -> torch.Tensor:
+    t = torch.as_tensor(x, dtype=torch.int32)
+    if not t.is_cuda:
+        t = t.to(device)
+    if t.device != device or not t.is_contiguous():
+        t = t.to(device).contiguous()
+    return t
+
+
+def sample_batched(xyz: torch.Tensor, offsets, m, starts=None, m_total: int | None = None, n_vox: int = 0,
+                   tile: int = 0, groups: int = 0, lookahead: int = 0, flags: int = 0,
+                   ws: BatchWorkspace | None = None, out_idx=None, out_d2=None, check: bool = True,
+                   shell: float = 0.0):
+    """rfps_sample_batched on torch's current stream.
+
+    offsets (int32 [B+1]), m (int32 [B]) and starts (int32 [B] or None) may be
+    host sequences or device tensors; m_total is read from m when m is on the
+    host, else it must be given.  Returns (idx, d2), both [m_total]: the
+    selections of cloud c follow those of clouds 0..c-1, as local indices.
+    With check=False nothing waits for the device (graph capture).
+    """
+    _check_xyz(xyz)
+    dev = xyz.device
+    n = xyz.shape[0]
+    if m_total is None:
+        if isinstance(m, torch.Tensor) and m.is_cuda:
+            raise ValueError("m_total is required when m is a device tensor")
+        m_total = int(sum(int(v) for v in m))
+    offsets_d = _i32_dev(offsets, dev)
+    m_d = _i32_dev(m, dev)
+    starts_d = None if starts is None else _i32_dev(starts, dev)
+    batch = offsets_d.numel() - 1
+    if m_d.numel() != batch or (starts_d is not None and starts_d.numel() != batch):
+        raise ValueError("offsets, m and starts disagree on the batch size")
+    if ws is None or not ws.fits(n, batch, n_vox, shell):
+        ws = BatchWorkspace(n, batch, dev, n_vox=n_vox, shell=shell)
+    if out_idx is None:
+        out_idx = torch.empty(m_total, dtype=torch.int32, device=dev)
+    if out_d2 is None:
+        out_d2 = torch.empty(m_total, dtype=torch.float32, device=dev)
+    p = _params(n_vox, tile, groups, flags, lookahead, shell)
+    _check(lib().rfps_sample_batched(xyz.data_ptr(), n, offsets_d.data_ptr(), m_d.data_ptr(),
+                                     0 if starts_d is None else starts_d.data_ptr(), batch, int(m_total),
+                                     ctypes.byref(p), ws.ptr, ws.nbytes, out_idx.data_ptr(), out_d2.data_ptr(),
+                                     _stream(dev)), "rfps_sample_batched")
+    if check:
+        _check(lib().rfps_batched_read_status(ws.ptr, ws.nbytes, _stream(dev)), "device status")
+    return out_idx, out_d2
+
+
+def batched_read_status(ws: BatchWorkspace) -> int:
+    return int(lib().rfps_batched_read_status(ws.ptr, ws.nbytes, _stream(ws.device)))
+
+
+def batched_read_telemetry(ws: BatchWorkspace) -> dict:
+    t = rfps_telemetry()
+    _check(lib().rfps_batched_read_telemetry(ws.ptr, ws.nbytes, _stream(ws.device), ctypes.byref(t)),
+           "rfps_batched_read_telemetry")
+    return t.as_dict()
+
+
+def autotune_batched(xyz: torch.Tensor, offsets, m, starts=None, n_vox: int = 0, tile: int = 0,
+                     groups: int = 0, lookahead: int = 0, flags: int = 0, reps: int = 3,
+                     ws: BatchWorkspace | None = None):
+    """rfps_autotune_batched: returns ({n_vox, tile, groups, lookahead, flags}, median ms, (idx, d2))."""
+    _check_xyz(xyz)
+    dev = xyz.device
+    n = xyz.shape[0]
+    m_host = [int(v) for v in (m.tolist() if isinstance(m, torch.Tensor) else m)]
+    m_total = sum(m_host)
+    offsets_d, m_d = _i32_dev(offsets, dev), _i32_dev(m_host, dev)
+    starts_d = None if starts is None else _i32_dev(starts, dev)
+    batch = offsets_d.numel() - 1
+    if ws is None or not ws.fits(n, batch, n_vox):
+        ws = BatchWorkspace(n, batch, dev, n_vox=n_vox)
+    out_idx = torch.empty(m_total, dtype=torch.int32, device=dev)
+    out_d2 = torch.empty(m_total, dtype=torch.float32, device=dev)
+    base = _params(n_vox, tile, groups, flags, lookahead)
+    best = rfps_params()
+    ms = ctypes.c_float(0.0)
+    _check(lib().rfps_autotune_batched(xyz.data_ptr(), n, offsets_d.data_ptr(), m_d.data_ptr(),
+                                       0 if starts_d is None else starts_d.data_ptr(), batch, m_total,
+                                       ctypes.byref(base), int(reps), ws.ptr, ws.nbytes, out_idx.data_ptr(),
+                                       out_d2.data_ptr(), _stream(dev), ctypes.byref(best), ctypes.byref(ms)),
+           "rfps_autotune_batched")
+    chosen = {k: int(getattr(best, k)) for k, _ in rfps_params._fields_}
+    return chosen, float(ms.value), (out_idx, out_d2)
+
+
+# ---------------------------------------------------------------------------
+# Voxel-parameter network (include/rfps_mlp.h)
+# ---------------------------------------------------------------------------
+MLP_INPUTS, MLP_OUTPUTS, MLP_CANDIDATES, MLP_PARAMS = 516, 72, 36, 41928
+
+
+def mlp_candidate(k: int):
+    """(n_vox, shell spacing) of candidate k."""
+    nv = ctypes.c_int32(0)
+    sh = ctypes.c_float(0.0)
+    if lib().rfps_mlp_candidate(int(k), ctypes.byref(nv), ctypes.byref(sh)) != 0:
+        raise ValueError("candidate out of range")
+    return int(nv.value), float(sh.value)
+
+
+class MLP:
+    """Model state and a workspace for up to `rows` rows, in device memory."""
+
+    def __init__(self, device, rows: int = 1):
+        L = lib()
+        self.device = device
+        self.state_bytes = int(L.rfps_mlp_state_size())
+        self.state, self.state_ptr = _workspace(self.state_bytes, device)
+        self.rows = 0
+        self._reserve(max(1, int(rows)))
+
+    def _reserve(self, rows: int):
+        if rows <= self.rows:
+            return
+        nbytes = int(lib().rfps_mlp_workspace_size(int(rows)))
+        if nbytes == 0:
+            raise RfpsError(1, "rfps_mlp_workspace_size")
+        self.ws, self.ws_ptr = _workspace(nbytes, self.device)
+        self.ws_bytes, self.rows = nbytes, int(rows)
+
+    def load(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())
+        if p.size != MLP_PARAMS:
+            raise ValueError("expected %d parameters" % MLP_PARAMS)
+        _check(lib().rfps_mlp_load(self.state_ptr, self.state_bytes, p.ctypes.data, _stream(self.device)),
+               "rfps_mlp_load")
+
+    def save(self):
+        import numpy as np
+        p = np.empty(MLP_PARAMS, dtype=np.float32)
+        _check(lib().rfps_mlp_save(self.state_ptr, self.state_bytes, p.ctypes.data, _stream(self.device)),
+               "rfps_mlp_save")
+        return p
+
+    def features(self, xyz: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        _check_xyz(xyz)
+        if out is None:
+            out = torch.empty(MLP_INPUTS, dtype=torch.float32, device=self.device)
+        _check(lib().rfps_mlp_features(xyz.data_ptr(), xyz.shape[0], self.ws_ptr, self.ws_bytes, out.data_ptr(),
+                                       _stream(self.device)), "rfps_mlp_features")
+        return out
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        x = x.reshape(-1, MLP_INPUTS).contiguous()
+        self._reserve(x.shape[0])
+        y = torch.empty(x.shape[0], MLP_OUTPUTS, dtype=torch.float32, device=self.device)
+        _check(lib().rfps_mlp_forward(self.state_ptr, self.state_bytes, x.data_ptr(), x.shape[0], self.ws_ptr,
+                                      self.ws_bytes, y.data_ptr(), _stream(self.device)), "rfps_mlp_forward")
+        return y
+
+    def gradient(self, x, t, w=None):
+        x = x.reshape(-1, MLP_INPUTS).contiguous()
+        self._reserve(x.shape[0])
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check(lib().rfps_mlp_gradient(self.state_ptr, self.state_bytes, x.data_ptr(), t.data_ptr(),
+                                       0 if w is None else w.data_ptr(), x.shape[0], self.ws_ptr, self.ws_bytes,
+                                       g.data_ptr(), loss.data_ptr(), _stream(self.device)), "rfps_mlp_gradient")
+        return g, loss
+
+    def train_step(self, x, t, w=None, lr: float = 1e-3, loss: torch.Tensor | None = None):
+        x = x.reshape(-1, MLP_INPUTS)
+        self._reserve(x.shape[0])
+        _check(lib().rfps_mlp_train_step(self.state_ptr, self.state_bytes, x.data_ptr(), t.data_ptr(),
+                                         0 if w is None else w.data_ptr(), x.shape[0], float(lr), self.ws_ptr,
+                                         self.ws_bytes, 0 if loss is None else loss.data_ptr(),
+                                         _stream(self.device)), "rfps_mlp_train_step")
+
+    def choose(self, feat: torch.Tensor, default_cand: int, margin: float = 0.0):
+        """(chosen candidate, predictions [72]) -- waits for the device."""
+        choice = torch.empty(1, dtype=torch.int32, device=self.device)
+        y = torch.empty(MLP_OUTPUTS, dtype=torch.float32, device=self.device)
+        _check(lib().rfps_mlp_choose(self.state_ptr, self.state_bytes, feat.data_ptr(), int(default_cand),
+                                     float(margin), self.ws_ptr, self.ws_bytes, choice.data_ptr(), y.data_ptr(),
+                                     _stream(self.device)), "rfps_mlp_choose")
+        return int(choice.item()), y

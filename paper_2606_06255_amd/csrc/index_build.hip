@@ -83,42 +83,38 @@ __global__ __launch_bounds__(kBlock) void k_bbox(const float *__restrict__ xyz, 
 }
 
 // Voxel edge L = alpha * max(E) / n_vox with alpha = 1 + 1e-4 (eq. voxel_size);
-// a cloud of identical points gets L = 1 (one voxel).
-__global__ void k_grid(IndexHeader *hdr, int n_vox)
+// a cloud of identical points gets L = 1 (one voxel).  The range shells (if
+// any) are centred on the bounding-box centre.
+__global__ void k_grid(IndexHeader *hdr, int n_vox, double shell_inv, uint32_t shell_cap)
 {
-    if (threadIdx.x != 0 || hdr->build_status)
+    if (threadIdx.x != 0)
         return;
     double E = 0.0;
     for (int a = 0; a < 3; ++a) {
-        float lo = ord2f(hdr->bb[a]), hi = ord2f(hdr->bb[3 + a]);
+        const float lo = ord2f(hdr->bb[a]), hi = ord2f(hdr->bb[3 + a]);
         hdr->pmin[a] = (double)lo;
-        double e = (double)hi - (double)lo;
+        hdr->origin[a] = 0.5 * ((double)lo + (double)hi);
+        const double e = (double)hi - (double)lo;
         E = e > E ? e : E;
     }
     const double alpha = 1.0 + 1e-4;
-    hdr->L = E > 0.0 ? alpha * E / (double)n_vox : 1.0;
+    // a failed build still gets a finite edge: the keys are then meaningless
+    // but every index computed from them stays in range
+    hdr->L = (E > 0.0 && E < INFINITY && !hdr->build_status) ? alpha * E / (double)n_vox : 1.0;
+    hdr->shell_inv = shell_inv;
+    hdr->shell_cap = shell_cap;
 }
 
-// Voxel id of every point (clamped, FP64 quotient) and the identity payload.
+// Voxel key of every point and the identity payload.
 __global__ __launch_bounds__(kBlock) void k_voxel_key(const float *__restrict__ xyz, int n,
                                                       const IndexHeader *__restrict__ hdr, int n_vox,
                                                       uint32_t *__restrict__ key, uint32_t *__restrict__ val)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
-    const double L = hdr->L;
-    const double top = (double)(n_vox - 1);
-    uint32_t v[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double q = floor(((double)xyz[3 * (size_t)i + a] - hdr->pmin[a]) / L);
-        q = q < 0.0 ? 0.0 : q;
-        q = q > top ? top : q;
-        v[a] = (uint32_t)q;
-    }
-    const uint32_t nv = (uint32_t)n_vox;
-    key[i] = (v[2] * nv + v[1]) * nv + v[0];
+    key[i] = voxel_key(xyz[3 * (size_t)i], xyz[3 * (size_t)i + 1], xyz[3 * (size_t)i + 2], hdr->pmin, hdr->L,
+                       (uint32_t)n_vox, hdr->origin, hdr->shell_inv, hdr->shell_cap);
     val[i] = (uint32_t)i;
 }
 
@@ -413,7 +409,7 @@ hipError_t launch_build_index(const IndexView &v, const float *xyz, hipStream_t 
     const int n = v.n;
     k_build_reset<<<1, kWave, 0, s>>>(v.hdr);
     k_bbox<<<std::min(blocks_for(n, kBlock * 4), 512), kBlock, 0, s>>>(xyz, n, v.hdr);
-    k_grid<<<1, kWave, 0, s>>>(v.hdr, v.n_vox);
+    k_grid<<<1, kWave, 0, s>>>(v.hdr, v.n_vox, v.shell_inv, v.shell_cap);
     k_voxel_key<<<blocks_for(n, kBlock), kBlock, 0, s>>>(xyz, n, v.hdr, v.n_vox, v.keyA, v.valA);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -444,6 +440,256 @@ hipError_t launch_build_index(const IndexView &v, const float *xyz, hipStream_t 
         return e;
     k_tiles<<<std::min(blocks_for(n, kWavesPerBlock), 2048), kBlock, 0, s>>>(
         v.vstart, v.tbase, v.hdr, v.tile, v.xs, v.ys, v.zs, v.tstart, v.tcnt, v.tcx, v.tcy, v.tcz, v.trad);
+    return hipGetLastError();
+}
+
+}  // namespace rfps
+
+// ---------------------------------------------------------------------------
+// Batched index: the clouds of a batch share one sorted index.  A point of
+// cloud c gets the key base_c + V_id (V_id on the cloud's own grid), so
+// voxels and tiles never mix clouds and the tiles of every cloud are one
+// contiguous range.
+// ---------------------------------------------------------------------------
+namespace rfps {
+
+// Cloud of global point i: the largest c with offsets[c] <= i.
+__device__ __forceinline__ int cloud_of(const int32_t *off, int B, int i)
+{
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+
+// Clears the header, the per-cloud boxes, the batch state and the exchange
+// board (epochs restart at 1 in every call).
+__global__ __launch_bounds__(kBlock) void k_batch_reset(IndexHeader *hdr, BatchCtl bc, uint32_t *cl_bb,
+                                                        BatchState *st, unsigned long long *board)
+{
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x, nth = gridDim.x * blockDim.x;
+    if (tid == 0) {
+        hdr->build_status = 0;
+        hdr->sample_status = 0;
+        hdr->n_voxels = 0;
+        hdr->n_tiles = 0;
+        hdr->last_m = (uint32_t)bc.m_total;
+        hdr->trace_n = 0;
+        for (int t = 0; t < kTeleFields; ++t)
+            hdr->tele[t] = 0;
+        st->joined = 0;
+        st->next = 0;
+        for (int x = 0; x < kMaxXcds; ++x)
+            st->xcd_count[x] = 0;
+    }
+    for (int c = tid; c < bc.batch; c += nth) {
+        for (int a = 0; a < 3; ++a) {
+            cl_bb[6 * c + a] = 0xffffffffu;
+            cl_bb[6 * c + 3 + a] = 0u;
+        }
+    }
+    for (int w = tid; w < kBoardWords; w += nth)
+        board[w] = 0ull;
+}
+
+// Checks the batch description (offsets from 0 to n with every cloud
+// non-empty, 1 <= m_c <= N_c, start indices inside their clouds, sum of m
+// equal to the output length), then computes the output offsets, the bins
+// per axis and the first key of every cloud.  One workgroup; the prefix sums
+// run on one thread (batch <= 4096).
+__global__ void k_batch_setup(IndexHeader *hdr, BatchCtl bc, int n, uint32_t *cl_nvox, uint32_t *cl_base)
+{
+    __shared__ uint32_t s_bad;
+    if (threadIdx.x == 0)
+        s_bad = (bc.offsets[0] != 0 || bc.offsets[bc.batch] != n) ? 1u : 0u;
+    __syncthreads();
+    for (int c = threadIdx.x; c < bc.batch; c += blockDim.x) {
+        const int nc = bc.offsets[c + 1] - bc.offsets[c];
+        const int mc = bc.m[c];
+        const int sc = bc.starts ? bc.starts[c] : 0;
+        if (nc < 1 || mc < 1 || mc > nc || sc < 0 || sc >= nc)
+            atomicOr(&s_bad, 1u);
+        cl_nvox[c] = (uint32_t)(bc.fixed_n_vox ? bc.fixed_n_vox : default_n_vox_rule(nc > 0 ? nc : 1));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long base = 0, out = 0;
+        for (int c = 0; c < bc.batch; ++c) {
+            cl_base[c] = (uint32_t)base;
+            bc.out_offsets[c] = (uint32_t)out;
+            const unsigned long long nv = cl_nvox[c];
+            base += nv * nv * nv * shell_cap_for(cl_nvox[c], bc.shell_inv > 0.0);
+            out += (unsigned long long)(bc.m[c] > 0 ? bc.m[c] : 0);
+        }
+        cl_base[bc.batch] = (uint32_t)base;
+        bc.out_offsets[bc.batch] = (uint32_t)out;
+        if (s_bad || out != (unsigned long long)bc.m_total)
+            set_status(&hdr->build_status, RFPS_ERR_INVALID_ARG);
+        else if (base > 0xffffffffull)
+            set_status(&hdr->build_status, RFPS_ERR_UNSUPPORTED);
+    }
+}
+
+// Per-cloud bounding boxes; flags non-finite coordinates.  A wavefront whose
+// points all belong to one cloud reduces before its atomics.
+__global__ __launch_bounds__(kBlock) void k_bbox_batch(const float *__restrict__ xyz, int n, BatchCtl bc,
+                                                       uint32_t *cl_bb, IndexHeader *hdr)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int i0 = blockIdx.x * blockDim.x; i0 < n; i0 += gridDim.x * blockDim.x) {
+        const int i = i0 + threadIdx.x;
+        const bool valid = i < n;
+        float p[3] = {0.0f, 0.0f, 0.0f};
+        int c = 0;
+        bool bad = false;
+        if (valid) {
+            c = cloud_of(bc.offsets, bc.batch, i);
+            for (int a = 0; a < 3; ++a) {
+                p[a] = xyz[3 * (size_t)i + a];
+                bad |= !isfinite(p[a]);
+            }
+        }
+        if (__any(bad) && lane == 0)
+            set_status(&hdr->build_status, RFPS_ERR_NONFINITE);
+        const int c0 = __builtin_amdgcn_readfirstlane(c);
+        if (__all(!valid || c == c0)) {
+            for (int a = 0; a < 3; ++a) {
+                const float lo = wave_min_f32(valid ? p[a] : INFINITY);
+                const float hi = wave_max_f32(valid ? p[a] : -INFINITY);
+                if (lane == 0 && lo <= hi) {
+                    atomicMin(&cl_bb[6 * c0 + a], f2ord(lo));
+                    atomicMax(&cl_bb[6 * c0 + 3 + a], f2ord(hi));
+                }
+            }
+        } else if (valid) {
+            for (int a = 0; a < 3; ++a) {
+                atomicMin(&cl_bb[6 * c + a], f2ord(p[a]));
+                atomicMax(&cl_bb[6 * c + 3 + a], f2ord(p[a]));
+            }
+        }
+    }
+}
+
+// Grid of every cloud: its own box and bins (eq. voxel_size).
+__global__ __launch_bounds__(kBlock) void k_grid_batch(IndexHeader *hdr, BatchCtl bc, const uint32_t *cl_bb,
+                                                       const uint32_t *cl_nvox, double *cl_pmin, double *cl_L)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= bc.batch)
+        return;
+    double E = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const float lo = ord2f(cl_bb[6 * c + a]), hi = ord2f(cl_bb[6 * c + 3 + a]);
+        cl_pmin[3 * c + a] = (double)lo;
+        const double e = (double)hi - (double)lo;
+        E = e > E ? e : E;
+    }
+    const double alpha = 1.0 + 1e-4;
+    // a failed build still gets a finite edge: the keys are then meaningless
+    // but every index computed from them stays in range
+    cl_L[c] = (E > 0.0 && E < INFINITY && !hdr->build_status) ? alpha * E / (double)cl_nvox[c] : 1.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_voxel_key_batch(const float *__restrict__ xyz, int n, BatchCtl bc,
+                                                            const uint32_t *__restrict__ cl_nvox,
+                                                            const uint32_t *__restrict__ cl_base,
+                                                            const double *__restrict__ cl_pmin,
+                                                            const double *__restrict__ cl_L,
+                                                            const uint32_t *__restrict__ cl_bb, uint32_t *key,
+                                                            uint32_t *val)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const int c = cloud_of(bc.offsets, bc.batch, i);
+    const uint32_t nv = cl_nvox[c];
+    double o[3];
+    for (int a = 0; a < 3; ++a)
+        o[a] = 0.5 * ((double)ord2f(cl_bb[6 * c + a]) + (double)ord2f(cl_bb[6 * c + 3 + a]));
+    key[i] = cl_base[c] + voxel_key(xyz[3 * (size_t)i], xyz[3 * (size_t)i + 1], xyz[3 * (size_t)i + 2],
+                                    cl_pmin + 3 * c, cl_L[c], nv, o, bc.shell_inv,
+                                    shell_cap_for(nv, bc.shell_inv > 0.0));
+    val[i] = (uint32_t)i;
+}
+
+// First tile of every cloud.  Tiles follow the key order, so the tiles of a
+// cloud are contiguous and clouds appear in index order; every cloud of a
+// valid batch has at least one tile.
+__global__ __launch_bounds__(kBlock) void k_tile_first(const uint32_t *__restrict__ tstart,
+                                                       const uint32_t *__restrict__ orig,
+                                                       const IndexHeader *__restrict__ hdr, BatchCtl bc,
+                                                       uint32_t *tile_first)
+{
+    const uint32_t NT = hdr->n_tiles;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < NT; t += gridDim.x * blockDim.x) {
+        const int c = cloud_of(bc.offsets, bc.batch, (int)orig[tstart[t]]);
+        const int cp = t ? cloud_of(bc.offsets, bc.batch, (int)orig[tstart[t - 1]]) : -1;
+        for (int q = cp + 1; q <= c; ++q)
+            tile_first[q] = t;
+        if (t == NT - 1)
+            tile_first[bc.batch] = NT;
+    }
+}
+
+// Clouds by decreasing cost N_c * m_c, ties by index: the teams take them in
+// this order, so the longest jobs start first.
+__global__ void k_batch_order(BatchCtl bc, int32_t *order)
+{
+    for (int c = threadIdx.x; c < bc.batch; c += blockDim.x) {
+        const long long cc = (long long)(bc.offsets[c + 1] - bc.offsets[c]) * (long long)bc.m[c];
+        int rank = 0;
+        for (int d = 0; d < bc.batch; ++d) {
+            const long long cd = (long long)(bc.offsets[d + 1] - bc.offsets[d]) * (long long)bc.m[d];
+            rank += (cd > cc) || (cd == cc && d < c);
+        }
+        order[rank] = c;
+    }
+}
+
+hipError_t launch_build_batch(const IndexView &v, const float *xyz, hipStream_t s)
+{
+    const int n = v.n, B = v.bc.batch;
+    k_batch_reset<<<32, kBlock, 0, s>>>(v.hdr, v.bc, v.cl_bb, v.bstate, v.board);
+    k_batch_setup<<<1, kBlock, 0, s>>>(v.hdr, v.bc, n, v.cl_nvox, v.cl_base);
+    k_bbox_batch<<<std::min(blocks_for(n, kBlock), 1024), kBlock, 0, s>>>(xyz, n, v.bc, v.cl_bb, v.hdr);
+    k_grid_batch<<<blocks_for(B, kBlock), kBlock, 0, s>>>(v.hdr, v.bc, v.cl_bb, v.cl_nvox, v.cl_pmin, v.cl_L);
+    k_voxel_key_batch<<<blocks_for(n, kBlock), kBlock, 0, s>>>(xyz, n, v.bc, v.cl_nvox, v.cl_base, v.cl_pmin,
+                                                               v.cl_L, v.cl_bb, v.keyA, v.valA);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const int nblk = blocks_for(n, kRadixTile);
+    uint32_t *kin = v.keyA, *vin = v.valA, *kout = v.keyB, *vout = v.valB;
+    for (int pass = 0; pass < v.radix_passes; ++pass) {
+        k_radix_hist<<<nblk, kBlock, 0, s>>>(kin, n, 8 * pass, v.hist, nblk);
+        e = launch_scan(v.hist, v.hist, 256 * nblk, v.partials, nullptr, s);
+        if (e != hipSuccess)
+            return e;
+        k_radix_scatter<<<nblk, kBlock, 0, s>>>(kin, vin, kout, vout, n, 8 * pass, v.hist, nblk);
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    k_gather<<<blocks_for(n, kBlock), kBlock, 0, s>>>(xyz, v.orig, n, v.xs, v.ys, v.zs, v.inv);
+    k_heads<<<blocks_for(n, kBlock), kBlock, 0, s>>>(v.skey, n, v.flags);
+    e = launch_scan(v.flags, v.hscan, n, v.partials, &v.hdr->n_voxels, s);
+    if (e != hipSuccess)
+        return e;
+    k_voxels<<<blocks_for(n, kBlock), kBlock, 0, s>>>(v.flags, v.hscan, n, v.vstart);
+    k_tile_count<<<blocks_for(n, kBlock), kBlock, 0, s>>>(v.vstart, v.hdr, n, v.tile, v.tcount);
+    e = launch_scan(v.tcount, v.tbase, n, v.partials, &v.hdr->n_tiles, s);
+    if (e != hipSuccess)
+        return e;
+    k_tiles<<<std::min(blocks_for(n, kWavesPerBlock), 2048), kBlock, 0, s>>>(
+        v.vstart, v.tbase, v.hdr, v.tile, v.xs, v.ys, v.zs, v.tstart, v.tcnt, v.tcx, v.tcy, v.tcz, v.trad);
+    k_tile_first<<<std::min(blocks_for(n, kBlock), 1024), kBlock, 0, s>>>(v.tstart, v.orig, v.hdr, v.bc,
+                                                                          v.tile_first);
+    k_batch_order<<<1, kBlock, 0, s>>>(v.bc, v.order);
     return hipGetLastError();
 }
 

@@ -3,10 +3,12 @@
 // Host code only; the kernels live in index_build.hip, sample_rfps.hip and
 // sample_plain.hip.
 #include <math.h>
+#include <cmath>
 #include <string.h>
 
 #include <algorithm>
 #include <mutex>
+#include <vector>
 
 #include "rfps_internal.h"
 
@@ -59,11 +61,13 @@ const DeviceInfo *device_info()
     return &d;
 }
 
-// Index workspace layout.  Every segment is 256-byte aligned.
+// Index workspace layout.  Every segment is 256-byte aligned.  A batched
+// workspace appends the per-cloud arrays to the index of all its points.
 struct IndexLayout {
     size_t hdr, keyA, keyB, valA, valB, xs, ys, zs, inv, flags, hscan, vstart, tcount, tbase, tstart, tcnt, tcx,
         tcy, tcz, trad, partials, hist, board, trace, total;
-    int radix_passes, nblk;
+    size_t cl_pmin, cl_L, cl_bb, cl_nvox, cl_base, cl_out, tile_first, order, bstate;
+    int radix_passes, nblk, batch;
 };
 
 int bit_length(uint64_t v)
@@ -76,7 +80,10 @@ int bit_length(uint64_t v)
     return b;
 }
 
-IndexLayout layout_index(int n, int n_vox)
+// Sort passes for keys below `cells` (8 bits per pass, at least one).
+int passes_for(uint64_t cells) { return std::max(1, (bit_length(cells - 1) + 7) / 8); }
+
+IndexLayout layout_common(int n, int passes, int batch)
 {
     IndexLayout L;
     size_t cur = 0;
@@ -87,8 +94,8 @@ IndexLayout layout_index(int n, int n_vox)
     };
     const size_t N = (size_t)n;
     L.nblk = (n + kRadixTile - 1) / kRadixTile;
-    const uint64_t cells = (uint64_t)n_vox * n_vox * n_vox;
-    L.radix_passes = (bit_length(cells - 1) + 7) / 8;
+    L.radix_passes = passes;
+    L.batch = batch;
     const size_t scan_elems = std::max(N, (size_t)256 * L.nblk);
     L.hdr = take(sizeof(IndexHeader));
     L.keyA = take(4 * N);
@@ -114,13 +121,37 @@ IndexLayout layout_index(int n, int n_vox)
     L.hist = take(4 * (size_t)256 * L.nblk);
     L.board = take(8 * (size_t)kBoardWords);
     L.trace = take(8 * (size_t)2 * kTraceCap);
+    const size_t B = (size_t)batch;
+    L.cl_pmin = take(24 * B);
+    L.cl_L = take(8 * B);
+    L.cl_bb = take(24 * B);
+    L.cl_nvox = take(4 * B);
+    L.cl_base = take(4 * (B + 1));
+    L.cl_out = take(4 * (B + 1));
+    L.tile_first = take(4 * (B + 1));
+    L.order = take(4 * B);
+    L.bstate = take(sizeof(BatchState));
     L.total = align_up(cur);
     return L;
 }
 
-IndexView make_view(void *ws, int n, int n_vox, int tile)
+IndexLayout layout_index(int n, int n_vox, int shells)
 {
-    const IndexLayout L = layout_index(n, n_vox);
+    return layout_common(n, passes_for((uint64_t)n_vox * n_vox * n_vox * (uint64_t)shells), 0);
+}
+
+// A batch sorts by cloud-prefixed keys: with a fixed n_vox the key range is
+// known here; with the per-cloud rule it is only known on the device, so the
+// sort takes all four passes.
+IndexLayout layout_batch(int n, int batch, int fixed_n_vox, bool shells)
+{
+    const uint64_t n3 = (uint64_t)fixed_n_vox * fixed_n_vox * fixed_n_vox;
+    const int passes = fixed_n_vox ? passes_for((uint64_t)batch * n3 * shell_cap_for(fixed_n_vox, shells)) : 4;
+    return layout_common(n, std::min(passes, 4), batch);
+}
+
+IndexView make_view_l(void *ws, const IndexLayout &L, int n, int n_vox, int tile)
+{
     unsigned char *b = static_cast<unsigned char *>(ws);
     IndexView v;
     v.hdr = reinterpret_cast<IndexHeader *>(b + L.hdr);
@@ -154,6 +185,26 @@ IndexView make_view(void *ws, int n, int n_vox, int tile)
     v.n_vox = n_vox;
     v.tile = tile;
     v.radix_passes = L.radix_passes;
+    v.shell_inv = 0.0;
+    v.shell_cap = 1;
+    v.batch = L.batch;
+    v.bc = BatchCtl{};
+    v.cl_pmin = reinterpret_cast<double *>(b + L.cl_pmin);
+    v.cl_L = reinterpret_cast<double *>(b + L.cl_L);
+    v.cl_bb = reinterpret_cast<uint32_t *>(b + L.cl_bb);
+    v.cl_nvox = reinterpret_cast<uint32_t *>(b + L.cl_nvox);
+    v.cl_base = reinterpret_cast<uint32_t *>(b + L.cl_base);
+    v.bc.out_offsets = reinterpret_cast<uint32_t *>(b + L.cl_out);
+    v.tile_first = reinterpret_cast<uint32_t *>(b + L.tile_first);
+    v.order = reinterpret_cast<int32_t *>(b + L.order);
+    v.bstate = reinterpret_cast<BatchState *>(b + L.bstate);
+    return v;
+}
+
+IndexView make_view(void *ws, int n, int n_vox, int tile, int shells)
+{
+    IndexView v = make_view_l(ws, layout_index(n, n_vox, shells), n, n_vox, tile);
+    v.shell_cap = (uint32_t)shells;
     return v;
 }
 
@@ -163,8 +214,13 @@ bool params_valid(const rfps_params *p)
         return true;
     return p->n_vox >= 0 && p->n_vox <= kMaxNVox && p->tile >= 0 && p->tile <= kWave && p->groups >= 0 &&
            p->groups <= kMaxGroups && (p->flags & ~kKnownFlags) == 0 &&
-           (p->lookahead == 0 || p->lookahead == 2 || p->lookahead == 4 || p->lookahead == 8);
+           (p->lookahead == 0 || p->lookahead == 2 || p->lookahead == 4 || p->lookahead == 8) &&
+           p->shell_spacing >= 0.0f;  // also rejects NaN
 }
+
+bool use_shells(const rfps_params *p) { return p && p->shell_spacing > 0.0f && std::isfinite(p->shell_spacing); }
+double shell_inv_of(const rfps_params *p) { return use_shells(p) ? 1.0 / (double)p->shell_spacing : 0.0; }
+int resolve_shells(int n_vox, const rfps_params *p) { return (int)shell_cap_for((uint32_t)n_vox, use_shells(p)); }
 
 int resolve_n_vox(int n, const rfps_params *p) { return (p && p->n_vox) ? p->n_vox : rfps_default_n_vox(n); }
 int resolve_tile(const rfps_params *p) { return (p && p->tile) ? p->tile : kWave; }
@@ -220,7 +276,8 @@ size_t rfps_index_workspace_size(int32_t n, const rfps_params *params)
 {
     if (n < 1 || n > kMaxPoints || !params_valid(params))
         return 0;
-    return layout_index(n, resolve_n_vox(n, params)).total;
+    const int n_vox = resolve_n_vox(n, params);
+    return layout_index(n, n_vox, resolve_shells(n_vox, params)).total;
 }
 
 rfps_status rfps_build_index(const float *xyz, int32_t n, const rfps_params *params, void *ws, size_t ws_bytes,
@@ -230,20 +287,22 @@ rfps_status rfps_build_index(const float *xyz, int32_t n, const rfps_params *par
         return RFPS_ERR_INVALID_ARG;
     const int n_vox = resolve_n_vox(n, params);
     const int tile = resolve_tile(params);
-    if (!ws || !aligned(ws) || ws_bytes < layout_index(n, n_vox).total)
+    const int shells = resolve_shells(n_vox, params);
+    if (!ws || !aligned(ws) || ws_bytes < layout_index(n, n_vox, shells).total)
         return RFPS_ERR_WORKSPACE;
     const DeviceInfo *d = device_info();
     if (!d)
         return RFPS_ERR_DEVICE;
     if (!d->ok)
         return RFPS_ERR_UNSUPPORTED;
-    const IndexView v = make_view(ws, n, n_vox, tile);
+    IndexView v = make_view(ws, n, n_vox, tile, shells);
+    v.shell_inv = shell_inv_of(params);
     if (launch_build_index(v, xyz, static_cast<hipStream_t>(stream)) != hipSuccess)
         return RFPS_ERR_DEVICE;
     out->n = n;
     out->n_vox = n_vox;
     out->tile = tile;
-    out->reserved = 0;
+    out->shells = shells;
     out->ws = ws;
     out->ws_bytes = ws_bytes;
     return RFPS_OK;
@@ -252,9 +311,11 @@ rfps_status rfps_build_index(const float *xyz, int32_t n, const rfps_params *par
 static rfps_status check_index(const rfps_index *index)
 {
     if (!index || index->n < 1 || index->n > kMaxPoints || index->n_vox < 1 || index->n_vox > kMaxNVox ||
-        index->tile < 1 || index->tile > kWave)
+        index->tile < 1 || index->tile > kWave || index->shells < 1 || index->shells > kMaxShells ||
+        (uint64_t)index->n_vox * index->n_vox * index->n_vox * (uint64_t)index->shells > (1ull << 32))
         return RFPS_ERR_INVALID_ARG;
-    if (!index->ws || !aligned(index->ws) || index->ws_bytes < layout_index(index->n, index->n_vox).total)
+    if (!index->ws || !aligned(index->ws) ||
+        index->ws_bytes < layout_index(index->n, index->n_vox, index->shells).total)
         return RFPS_ERR_WORKSPACE;
     return RFPS_OK;
 }
@@ -285,7 +346,7 @@ rfps_status rfps_sample(const rfps_index *index, int32_t m, int32_t start, const
     L.lds_budget = (uint32_t)((d->max_lds - stat - 256) & ~(size_t)255);
     if (L.G > d->cus)
         return RFPS_ERR_UNSUPPORTED;
-    const IndexView v = make_view(index->ws, index->n, index->n_vox, index->tile);
+    const IndexView v = make_view(index->ws, index->n, index->n_vox, index->tile, index->shells);
     hipError_t e = launch_rfps_sample(v, m, start, L, out_idx, out_d2, static_cast<hipStream_t>(stream));
     if (e == hipErrorCooperativeLaunchTooLarge)
         return RFPS_ERR_UNSUPPORTED;
@@ -356,7 +417,7 @@ int32_t rfps_read_trace(const rfps_index *index, void *stream, uint64_t *out, in
         return -1;
     int32_t cnt = (int32_t)h.trace_n;
     cnt = std::min(std::min(cnt, cap), kTraceCap);
-    const IndexLayout L = layout_index(index->n, index->n_vox);
+    const IndexLayout L = layout_index(index->n, index->n_vox, index->shells);
     if (cnt > 0 && hipMemcpy(out, static_cast<unsigned char *>(index->ws) + L.trace, 16 * (size_t)cnt,
                              hipMemcpyDeviceToHost) != hipSuccess)
         return -1;
@@ -421,6 +482,217 @@ rfps_status rfps_read_plain_status(const void *ws, size_t ws_bytes, void *stream
     if (hipMemcpy(&w, ws, sizeof w, hipMemcpyDeviceToHost) != hipSuccess)
         return RFPS_ERR_DEVICE;
     return (rfps_status)w;
+}
+
+// ---------------------------------------------------------------------------
+// Batches of clouds
+// ---------------------------------------------------------------------------
+size_t rfps_batched_workspace_size(int32_t n, int32_t batch, const rfps_params *params)
+{
+    if (n < 1 || n > kMaxPoints || batch < 1 || batch > kMaxBatch || batch > n || !params_valid(params))
+        return 0;
+    return layout_batch(n, batch, params ? params->n_vox : 0, use_shells(params)).total;
+}
+
+rfps_status rfps_sample_batched(const float *xyz, int32_t n, const int32_t *offsets, const int32_t *m,
+                                const int32_t *starts, int32_t batch, int32_t m_total, const rfps_params *params,
+                                void *ws, size_t ws_bytes, int32_t *out_idx, float *out_d2, void *stream)
+{
+    if (!xyz || !offsets || !m || !out_idx || n < 1 || n > kMaxPoints || batch < 1 || batch > kMaxBatch ||
+        batch > n || m_total < batch || m_total > n || !params_valid(params))
+        return RFPS_ERR_INVALID_ARG;
+    const uint32_t flags = params ? params->flags : 0u;
+    if (flags & (RFPS_F_NO_PRUNE | RFPS_F_SINGLE_PICK | RFPS_F_TRACE))
+        return RFPS_ERR_UNSUPPORTED;
+    const int fixed_n_vox = params ? params->n_vox : 0;
+    const IndexLayout BL = layout_batch(n, batch, fixed_n_vox, use_shells(params));
+    if (!ws || !aligned(ws) || ws_bytes < BL.total)
+        return RFPS_ERR_WORKSPACE;
+    const DeviceInfo *d = device_info();
+    if (!d)
+        return RFPS_ERR_DEVICE;
+    if (!d->ok || d->cus % kMaxXcds != 0 || d->cus > kMaxGroups)
+        return RFPS_ERR_UNSUPPORTED;
+    const int per_xcd = d->cus / kMaxXcds;
+    const int T = (params && params->groups) ? params->groups : per_xcd;
+    const long long teams = d->cus / std::max(T, 1);
+    if (T < 2 || per_xcd % T != 0 || teams * (2 * T + 1) * kMaxSlotWords > kBoardWords)
+        return RFPS_ERR_UNSUPPORTED;
+    SampleLaunch L;
+    L.G = d->cus;
+    L.flags = flags;
+    L.R = (params && params->lookahead) ? params->lookahead : kDefaultLookahead;
+    const size_t stat = rfps_sampler_static_lds(L.R);
+    if (stat == 0 || (size_t)d->max_lds <= stat + 1024)
+        return RFPS_ERR_UNSUPPORTED;
+    L.lds_budget = (uint32_t)((d->max_lds - stat - 256) & ~(size_t)255);
+
+    IndexView v = make_view_l(ws, BL, n, fixed_n_vox, resolve_tile(params));
+    v.bc.batch = batch;
+    v.bc.team_size = T;
+    v.bc.per_xcd = per_xcd;
+    v.bc.fixed_n_vox = fixed_n_vox;
+    v.bc.shell_inv = shell_inv_of(params);
+    v.bc.m_total = m_total;
+    v.bc.offsets = offsets;
+    v.bc.m = m;
+    v.bc.starts = starts;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_build_batch(v, xyz, s);
+    if (e == hipSuccess)
+        e = launch_rfps_rounds_batched(v, L, out_idx, out_d2, s);
+    if (e == hipErrorCooperativeLaunchTooLarge)
+        return RFPS_ERR_UNSUPPORTED;
+    return e == hipSuccess ? RFPS_OK : RFPS_ERR_DEVICE;
+}
+
+static rfps_status read_header(const void *ws, size_t ws_bytes, void *stream, IndexHeader *h)
+{
+    if (!ws || !aligned(ws) || ws_bytes < sizeof(IndexHeader))
+        return RFPS_ERR_WORKSPACE;
+    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess)
+        return RFPS_ERR_DEVICE;
+    if (hipMemcpy(h, ws, sizeof *h, hipMemcpyDeviceToHost) != hipSuccess)
+        return RFPS_ERR_DEVICE;
+    return RFPS_OK;
+}
+
+rfps_status rfps_batched_read_status(const void *ws, size_t ws_bytes, void *stream)
+{
+    IndexHeader h;
+    const rfps_status st = read_header(ws, ws_bytes, stream, &h);
+    if (st != RFPS_OK)
+        return st;
+    return (rfps_status)(h.build_status ? h.build_status : h.sample_status);
+}
+
+rfps_status rfps_batched_read_telemetry(const void *ws, size_t ws_bytes, void *stream, rfps_telemetry *out)
+{
+    if (!out)
+        return RFPS_ERR_INVALID_ARG;
+    IndexHeader h;
+    const rfps_status st = read_header(ws, ws_bytes, stream, &h);
+    if (st != RFPS_OK)
+        return st;
+    memcpy(out, h.tele, sizeof *out);
+    const DeviceInfo *d = device_info();
+    out->tick_hz = d ? (int64_t)d->wall_hz : 0;
+    return RFPS_OK;
+}
+
+rfps_status rfps_autotune_batched(const float *xyz, int32_t n, const int32_t *offsets, const int32_t *m,
+                                  const int32_t *starts, int32_t batch, int32_t m_total, const rfps_params *base,
+                                  int32_t reps, void *ws, size_t ws_bytes, int32_t *out_idx, float *out_d2,
+                                  void *stream, rfps_params *best, float *best_ms)
+{
+    if (!best || reps < 1 || reps > 100 || !params_valid(base))
+        return RFPS_ERR_INVALID_ARG;
+    const DeviceInfo *d = device_info();
+    if (!d)
+        return RFPS_ERR_DEVICE;
+    if (!d->ok || d->cus % kMaxXcds != 0)
+        return RFPS_ERR_UNSUPPORTED;
+    const int per_xcd = d->cus / kMaxXcds;
+    rfps_params b0 = base ? *base : rfps_params{0, 0, 0, 0, 0u};
+    std::vector<int> Ts, Rs, tiles;
+    for (int t = per_xcd; t >= 4; t /= 2)
+        if (per_xcd % t == 0 && (!b0.groups || b0.groups == t))
+            Ts.push_back(t);
+    for (int r : {2, 4, 8})
+        if (!b0.lookahead || b0.lookahead == r)
+            Rs.push_back(r);
+    for (int t : {32, 64})
+        if (!b0.tile || b0.tile == t)
+            tiles.push_back(t);
+    if (b0.groups && Ts.empty())
+        Ts.push_back(b0.groups);  // let rfps_sample_batched judge it
+    if (b0.tile && tiles.empty())
+        tiles.push_back(b0.tile);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t ev0, ev1;
+    if (hipEventCreate(&ev0) != hipSuccess)
+        return RFPS_ERR_DEVICE;
+    if (hipEventCreate(&ev1) != hipSuccess) {
+        hipEventDestroy(ev0);
+        return RFPS_ERR_DEVICE;
+    }
+    std::vector<int32_t> ref, cur;
+    bool have_ref = false;
+    float best_t = INFINITY;
+    rfps_params bp{};
+    rfps_status result = RFPS_OK;
+    for (int T : Ts) {
+        for (int R : Rs) {
+            for (int tile : tiles) {
+                rfps_params p = b0;
+                p.groups = T;
+                p.lookahead = R;
+                p.tile = tile;
+                // one untimed run: status, and the outputs against the first candidate
+                rfps_status st = rfps_sample_batched(xyz, n, offsets, m, starts, batch, m_total, &p, ws, ws_bytes,
+                                                     out_idx, out_d2, stream);
+                if (st == RFPS_OK)
+                    st = rfps_batched_read_status(ws, ws_bytes, stream);
+                if (st == RFPS_ERR_CAPACITY || st == RFPS_ERR_UNSUPPORTED)
+                    continue;  // this shape does not fit the device
+                if (st != RFPS_OK) {
+                    result = st;
+                    goto done;
+                }
+                cur.resize((size_t)m_total);
+                if (hipMemcpy(cur.data(), out_idx, 4 * (size_t)m_total, hipMemcpyDeviceToHost) != hipSuccess) {
+                    result = RFPS_ERR_DEVICE;
+                    goto done;
+                }
+                if (!have_ref) {
+                    ref = cur;
+                    have_ref = true;
+                } else if (cur != ref) {
+                    // every partition must give the same selections
+                    result = RFPS_ERR_INTERNAL;
+                    goto done;
+                }
+                std::vector<float> times;
+                for (int r = 0; r < reps; ++r) {
+                    hipEventRecord(ev0, s);
+                    st = rfps_sample_batched(xyz, n, offsets, m, starts, batch, m_total, &p, ws, ws_bytes, out_idx,
+                                             out_d2, stream);
+                    hipEventRecord(ev1, s);
+                    float ms = 0.0f;
+                    if (st != RFPS_OK || hipEventSynchronize(ev1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, ev0, ev1) != hipSuccess) {
+                        result = st != RFPS_OK ? st : RFPS_ERR_DEVICE;
+                        goto done;
+                    }
+                    times.push_back(ms);
+                }
+                std::sort(times.begin(), times.end());
+                const float med = times[times.size() / 2];
+                if (med < best_t) {
+                    best_t = med;
+                    bp = p;
+                }
+            }
+        }
+    }
+    if (!have_ref) {
+        result = RFPS_ERR_CAPACITY;
+        goto done;
+    }
+    // leave the outputs of the chosen configuration behind
+    result = rfps_sample_batched(xyz, n, offsets, m, starts, batch, m_total, &bp, ws, ws_bytes, out_idx, out_d2,
+                                 stream);
+    if (result == RFPS_OK)
+        result = rfps_batched_read_status(ws, ws_bytes, stream);
+    if (result == RFPS_OK) {
+        *best = bp;
+        if (best_ms)
+            *best_ms = best_t;
+    }
+done:
+    hipEventDestroy(ev0);
+    hipEventDestroy(ev1);
+    return result;
 }
 
 }  // extern "C"

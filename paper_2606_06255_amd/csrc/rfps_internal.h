@@ -20,8 +20,12 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kMaxGroups = 256;      // one exchange slot per thread of a workgroup
 constexpr int kSlotWords = 5;        // d2, ~orig, x, y, z, each tagged with the epoch
 constexpr int kMaxSlotWords = 64;    // largest slot of any exchange protocol (words)
-constexpr int kBoardWords = 2 * kMaxGroups * kMaxSlotWords;
+// Exchange board: a single cloud uses 2 * G slots; a batch gives every team
+// of T workgroups 2 * T slots plus a control slot, (256 / T) * (2T + 1) slots
+// in all, at most 576 for T >= 4.
+constexpr int kBoardWords = 640 * kMaxSlotWords;
 constexpr int kMaxNVox = 1024;
+constexpr int kMaxShells = 64;       // range shells of one cloud (the last one is open-ended)
 constexpr int kMaxPoints = 1 << 26;
 constexpr int kRadixItems = 8;       // keys per thread per radix tile
 constexpr int kRadixTile = kBlock * kRadixItems;
@@ -49,7 +53,34 @@ struct IndexHeader {
     uint32_t trace_n;    // entries the last traced call recorded
     double pmin[3];
     double L;            // voxel edge (eq. voxel_size)
+    double origin[3];    // centre of the range shells (bounding-box centre)
+    double shell_inv;    // 1 / shell spacing, 0 without shells
+    uint32_t shell_cap;  // shells in use (the last one is open-ended); 1 without shells
+    uint32_t pad_;
     unsigned long long tele[kTeleFields];  // rfps_telemetry, in its field order
+};
+
+constexpr int kMaxXcds = 8;      // XCDs of an MI355X; batched teams never span two
+constexpr int kMaxBatch = 4096;  // clouds per batched call
+
+// Batch description, passed by value to the kernels.
+struct BatchCtl {
+    int32_t batch;
+    int32_t team_size;       // T, workgroups sampling one cloud (divides per_xcd)
+    int32_t per_xcd;         // workgroups the launch places on every XCD
+    int32_t fixed_n_vox;     // 0: per-cloud default rule
+    double shell_inv;        // 1 / shell spacing, 0 without shells
+    int32_t m_total;         // sum of m over the batch (length of the outputs)
+    const int32_t *offsets;  // [batch+1] first point of every cloud (caller's device array)
+    const int32_t *m;        // [batch] selections per cloud (caller's device array)
+    const int32_t *starts;   // [batch] local start indices, or nullptr (all 0)
+    uint32_t *out_offsets;   // [batch+1] first output of every cloud (workspace, prefix sum of m)
+};
+
+// Per-call device state of a batch (in the workspace, cleared before every call).
+struct BatchState {
+    uint32_t joined, next;
+    uint32_t xcd_count[kMaxXcds];
 };
 
 // Device pointers into an index workspace (see layout_index in rfps_api.hip).
@@ -69,6 +100,17 @@ struct IndexView {
     unsigned long long *board;            // exchange board, kBoardWords words
     unsigned long long *trace;            // [kTraceCap][2]
     int32_t n, n_vox, tile, radix_passes;
+    double shell_inv;     // 1 / shell spacing, 0 without shells
+    uint32_t shell_cap;   // shells of the grid (1 without shells)
+    // batched index only (batch > 0)
+    int32_t batch;
+    BatchCtl bc;
+    double *cl_pmin, *cl_L;               // [batch][3], [batch] grid of every cloud
+    uint32_t *cl_bb;                      // [batch][6] order-preserving bounding boxes
+    uint32_t *cl_nvox, *cl_base;          // [batch] bins per axis, [batch+1] first key of every cloud
+    uint32_t *tile_first;                 // [batch+1] first tile of every cloud
+    int32_t *order;                       // [batch] clouds by decreasing cost
+    BatchState *bstate;
 };
 
 // ---------------------------------------------------------------------------
@@ -345,6 +387,90 @@ hipError_t launch_rfps_sample(const IndexView &v, int m, int start, const Sample
 size_t rfps_rounds_static_lds(int R);
 hipError_t launch_rfps_rounds(const IndexView &v, int m, int start, const SampleLaunch &L, int32_t *out_idx,
                               float *out_d2, hipStream_t s);
+// Writes -1 / NaN to all m outputs when the header records an error (sample_rfps.hip).
+hipError_t launch_sample_finalize(const IndexHeader *hdr, int m, int32_t *out_idx, float *out_d2, hipStream_t s);
+
+// Launches a persistent kernel of G workgroups of kBlock threads.  Outside
+// stream capture this is a cooperative launch, which fails unless all G
+// workgroups are resident together.  Under capture (a cooperative launch
+// cannot be recorded into a graph) it is an ordinary launch after the same
+// residency check from the occupancy calculator; every wait in the
+// persistent kernels is bounded, so even a shared device cannot hang them.
+inline hipError_t launch_persistent(const void *fn, int G, void **args, size_t lds, hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cs);
+    if (e != hipSuccess)
+        return e;
+    if (cs == hipStreamCaptureStatusNone)
+        return hipLaunchCooperativeKernel(fn, dim3(G), dim3(kBlock), args, (unsigned)lds, s);
+    int dev = 0, cus = 0, per_cu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess ||
+        (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess ||
+        (e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, lds)) != hipSuccess)
+        return e;
+    if ((long long)per_cu * cus < G)
+        return hipErrorCooperativeLaunchTooLarge;
+    return hipLaunchKernel(fn, dim3(G), dim3(kBlock), args, lds, s);
+}
+
+// Batched index build (index_build.hip) and batched sampling (sample_rounds.hip).
+hipError_t launch_build_batch(const IndexView &v, const float *xyz, hipStream_t s);
+hipError_t launch_rfps_rounds_batched(const IndexView &v, const SampleLaunch &L, int32_t *out_idx,
+                                      float *out_d2, hipStream_t s);
+// Shells a grid of n bins per axis may use: keys s * n^3 + V_id stay below 2^32.
+__host__ __device__ inline uint32_t shell_cap_for(uint32_t n, bool shells)
+{
+    if (!shells)
+        return 1u;
+    const unsigned long long n3 = (unsigned long long)n * n * n;
+    const unsigned long long cap = (1ull << 32) / n3;
+    return (uint32_t)(cap < (unsigned long long)kMaxShells ? cap : (unsigned long long)kMaxShells);
+}
+
+// Voxel key of a point (Sec. 3.2): V_id = v_z n^2 + v_y n + v_x with
+// v_a = clamp(floor((p_a - pmin_a) / L), 0, n - 1), the quotient in FP64.
+// With range shells (shell_inv > 0), a point at distance r from `o` lies in
+// shell s = min(floor(r / spacing), shell_cap - 1), which uses cubes of edge
+// (s + 1) L and ceil(n / (s + 1)) bins per axis from the same corner; its key
+// is s * n^3 + V_id on that coarser grid, so shells never share a voxel.
+// Any partition of the points into voxels leaves the sampling result
+// unchanged (the tile spheres enclose their members whatever the grid).
+__device__ __forceinline__ uint32_t voxel_key(float px, float py, float pz, const double *pmin, double L,
+                                              uint32_t n, const double *o, double shell_inv, uint32_t shell_cap)
+{
+    uint32_t s = 0;
+    if (shell_inv > 0.0) {
+        const double dx = (double)px - o[0], dy = (double)py - o[1], dz = (double)pz - o[2];
+        const double r = floor(sqrt(dx * dx + dy * dy + dz * dz) * shell_inv);
+        s = r < (double)(shell_cap - 1) ? (uint32_t)r : shell_cap - 1;
+    }
+    const uint32_t ns = (n + s) / (s + 1);
+    const double Ls = L * (double)(s + 1);
+    const double top = (double)(ns - 1);
+    const float p[3] = {px, py, pz};
+    uint32_t v[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double q = floor(((double)p[a] - pmin[a]) / Ls);
+        q = q > 0.0 ? q : 0.0;  // also maps NaN to 0
+        q = q < top ? q : top;
+        v[a] = (uint32_t)q;
+    }
+    return s * n * n * n + (v[2] * ns + v[1]) * ns + v[0];
+}
+
+// Per-cloud default voxel bins (same rule on host and device).
+__host__ __device__ inline int default_n_vox_rule(int n)
+{
+    const int cand[11] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256};
+    const double target = sqrt((double)(n > 0 ? n : 1) / 40.0);
+    int best = cand[0];
+    for (int q = 0; q < 11; ++q)
+        if (fabs(log((double)cand[q] / target)) < fabs(log((double)best / target)))
+            best = cand[q];
+    return best;
+}
 
 struct PlainLaunch {
     int variant;  // 0 persistent registers, 1 one workgroup

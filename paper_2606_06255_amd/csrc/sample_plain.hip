@@ -271,7 +271,7 @@ hipError_t launch_fps_plain(const float *xyz, int n, int m, int start, const Pla
             default: return hipErrorInvalidValue;
             }
             void *args[] = {&a};
-            e = hipLaunchCooperativeKernel(fn, dim3(L.G), dim3(kBlock), args, 0, s);
+            e = launch_persistent(fn, L.G, args, 0, s);
             if (e != hipSuccess)
                 return e;
         }

@@ -73,7 +73,9 @@ __global__ void k_sample_reset(IndexHeader *hdr, unsigned long long *board, int 
         if (out_d2)
             out_d2[0] = INFINITY;
     }
-    for (int w = tid; w < kBoardWords; w += gridDim.x * blockDim.x)
+    // the slots a team of G workgroups uses (both protocols fit in this span)
+    const int words = 2 * G * kMaxSlotWords;
+    for (int w = tid; w < words; w += gridDim.x * blockDim.x)
         board[w] = 0ull;
 }
 
@@ -429,13 +431,17 @@ hipError_t launch_rfps_sample(const IndexView &v, int m, int start, const Sample
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_budget);
             if (e != hipSuccess)
                 return e;
-            e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_rfps), dim3(L.G), dim3(kBlock), args,
-                                           L.lds_budget, s);
+            e = launch_persistent(reinterpret_cast<const void *>(k_rfps), L.G, args, L.lds_budget, s);
             if (e != hipSuccess)
                 return e;
         }
     }
-    k_sample_finalize<<<(m + kBlock - 1) / kBlock, kBlock, 0, s>>>(v.hdr, m, out_idx, out_d2);
+    return launch_sample_finalize(v.hdr, m, out_idx, out_d2, s);
+}
+
+hipError_t launch_sample_finalize(const IndexHeader *hdr, int m, int32_t *out_idx, float *out_d2, hipStream_t s)
+{
+    k_sample_finalize<<<(m + kBlock - 1) / kBlock, kBlock, 0, s>>>(hdr, m, out_idx, out_d2);
     return hipGetLastError();
 }
 

@@ -1,30 +1,41 @@
-// RadiusFPS-G with certified multi-pick rounds (the default sampler).
+// RadiusFPS-G with certified multi-pick rounds (the default sampler), for a
+// single cloud and for batches of clouds.
 //
-// Same ownership and LDS residency as k_rfps (tiles dealt round-robin to
-// workgroups), but one exchange now settles many selections.  A round:
+// A cloud is sampled by a team of G workgroups.  Rank r of the team owns the
+// cloud's tiles t with (t - first tile) % G == r (tiles of neighbouring voxels
+// land on different workgroups, so the unpruned work near a new sample
+// spreads over the team) and keeps their points (x, y, z, Dist_p, a private
+// lookahead copy of Dist_p, original index) and per-tile state (sphere, packed
+// Dist_v key, pruning threshold) in LDS for the whole cloud.  One exchange
+// settles a whole round of selections:
 //
 //   L  lookahead: every workgroup runs R steps of FPS on its own points only
-//      (a private copy of Dist_p, with the same spherical pruning), giving
-//      local candidates l_1..l_R with their local keys k_1 > .. > k_R and the
-//      bound k_{R+1}, the largest local key left after them;
+//      (on the private copy, with the same spherical pruning), giving local
+//      candidates l_1..l_R with local keys k_1 > .. > k_R and the bound
+//      k_{R+1}, the largest local key left after them;
 //   X  exchange: each workgroup publishes its candidates (coordinates, true
 //      round-start distance, local distance) and k_{R+1};
 //   M  merge: every workgroup replays the same deterministic merge.  Group g
 //      keeps a head h_g (how many of its candidates were taken).  Its bound
 //      B_g = k_{h_g+1} is an upper bound on the true key of every point of g:
-//      the true distances contain every pick of the round so far, which
-//      include l_1..l_{h_g}, so they are at most the local ones.  Hence the
-//      largest true key anywhere is at most max_g B_g, and if the head
-//      candidate of the group with the largest bound still has its true key
-//      equal to its local key (no other pick of the round reduced it), that
-//      candidate is exactly the next FPS selection (Sec. 3.1 rule, keys
-//      unique).  Otherwise the round ends;
+//      the true distances include every pick of the round so far, among them
+//      l_1..l_{h_g}, so they are at most the local ones.  Hence the largest
+//      true key anywhere is at most max_g B_g, and if the head candidate of
+//      the group with the largest bound still has its true key equal to its
+//      local key (no other pick of the round lowered it), that candidate is
+//      exactly the next FPS selection (the Sec. 3.1 rule; keys are unique).
+//      Otherwise the round ends;
 //   A  apply: all picks of the round update the true state (spherical test
 //      per tile and pick, point skip, strict update, tile-key resync).
 //
-// Every round certifies at least one selection (the largest bound is the
-// global maximum at round start, and nothing has reduced it yet), so the
-// kernel always terminates; the output equals plain FPS bit for bit.
+// Every round certifies at least one selection (at round start the largest
+// bound is attained by its own head), so the loop always terminates; the
+// output equals plain FPS bit for bit.
+//
+// Exchange scopes: a team spread over the device exchanges through
+// agent-scope atomics (coherent across XCDs); a team whose workgroups all
+// sit on one XCD exchanges through that XCD's L2 (plain stores, L1
+// invalidate before every poll), which halves the exchange latency.
 #include "rfps_internal.h"
 
 namespace rfps {
@@ -42,11 +53,34 @@ struct RoundArgs {
     int32_t n, m, start, G;
     uint32_t flags;
     uint32_t lds_budget;
+    // batched mode
+    BatchCtl bc;
+    BatchState *bstate;
+    const uint32_t *tile_first;  // [batch+1]
+    const int32_t *order;        // [batch] clouds by decreasing cost
 };
+
+// Selections one round may settle (the merge stops there; a shorter round is
+// always valid).  The merge keeps the round's picks in registers, eight per
+// lane of its wavefront.
+constexpr int kRoundPickSlots = 8;
+constexpr int kMaxRoundPicks = kWave * kRoundPickSlots;
 
 __host__ __device__ __forceinline__ uint32_t rounds_lds_need(uint32_t tiles, uint32_t pts, uint32_t G, uint32_t R)
 {
-    return tiles * 60u + pts * 24u + G * R * 28u + G * (R + 1u) * 8u + 128u;
+    return tiles * 60u + pts * 24u + G * R * 24u + G * (R + 1u) * 8u + kMaxRoundPicks * 16u + 128u;
+}
+
+// Capacity plan of one team of G workgroups over the tiles [tb, te).
+__device__ __forceinline__ bool team_fits(const uint32_t *tcnt, uint32_t tb, uint32_t te, int G, int R,
+                                          uint32_t budget, int rank)
+{
+    uint32_t tiles = 0, pts = 0;
+    for (uint32_t t = tb + rank; t < te; t += G) {
+        ++tiles;
+        pts += tcnt[t];
+    }
+    return pts <= 65535u && rounds_lds_need(tiles, pts, G, R) <= budget;
 }
 
 __global__ __launch_bounds__(kBlock) void k_rounds_plan(IndexHeader *hdr, const uint32_t *__restrict__ tcnt,
@@ -55,13 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_rounds_plan(IndexHeader *hdr, const 
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= G || hdr->build_status)
         return;
-    const uint32_t NT = hdr->n_tiles;
-    uint32_t tiles = 0, pts = 0;
-    for (uint32_t t = g; t < NT; t += G) {
-        ++tiles;
-        pts += tcnt[t];
-    }
-    if (pts > 65535u || rounds_lds_need(tiles, pts, G, R) > budget)
+    if (!team_fits(tcnt, 0, hdr->n_tiles, G, R, budget, g))
         set_status(&hdr->sample_status, RFPS_ERR_CAPACITY);
 }
 
@@ -83,35 +111,77 @@ __device__ __forceinline__ void tile_rekey(int lane, uint32_t lt, uint32_t ls, u
     }
 }
 
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_rfps_rounds(RoundArgs a)
+// ---------------------------------------------------------------------------
+// Exchange primitives for the two scopes.
+// ---------------------------------------------------------------------------
+enum class Scope { Agent, Xcd };
+
+template <Scope S>
+__device__ __forceinline__ void bstore(unsigned long long *p, unsigned long long v)
+{
+    if constexpr (S == Scope::Agent)
+        st_agent(p, v);
+    else
+        *reinterpret_cast<volatile unsigned long long *>(p) = v;  // written through to the XCD's L2
+}
+template <Scope S>
+__device__ __forceinline__ void binvalidate()
+{
+    if constexpr (S == Scope::Xcd)
+        asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+}
+template <Scope S>
+__device__ __forceinline__ unsigned long long bload(const unsigned long long *p)
+{
+    if constexpr (S == Scope::Agent)
+        return ld_agent(p);
+    else
+        return *reinterpret_cast<const volatile unsigned long long *>(p);
+}
+
+// Scalars every workgroup keeps in LDS (static shared memory of the kernels).
+struct RoundShared {
+    unsigned long long red[kWavesPerBlock];
+    uint32_t redi[kWavesPerBlock];
+    uint32_t scan[kWavesPerBlock];
+    uint32_t abort, list_n, npick;
+    uint32_t my[6 * 8 + 2];  // this workgroup's slot payload (R <= 8)
+};
+
+// Per-thread telemetry accumulators.
+struct RoundTele {
+    unsigned long long tests = 0, pruned = 0, visited = 0, skipped = 0, updated = 0, resync = 0;
+    unsigned long long ph[4] = {0, 0, 0, 0};
+    unsigned long long rounds = 0;
+};
+
+// What one team samples: tiles [tb, te) of the index, whose original indices
+// start at point_base (subtracted from the output), m selections from the
+// local start index, outputs at out_idx / out_d2 (already offset).
+struct CloudJob {
+    uint32_t tb, te, point_base;
+    int32_t m, start;
+    int32_t *out_idx;
+    float *out_d2;
+};
+
+// Samples one cloud.  Every thread of every workgroup of the team calls it.
+// `epoch` is the team's exchange counter: it only grows, so slots never need
+// clearing between clouds.  Returns false when an exchange failed (abort).
+template <int R, Scope S>
+__device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, int G, unsigned long long *board,
+                             uint32_t &epoch, unsigned char *smem, RoundShared &sh, RoundTele &tl,
+                             bool record_trace, bool clocks)
 {
     constexpr int W = 6 * R + 2;  // words per slot
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ unsigned long long s_red[kWavesPerBlock];
-    __shared__ uint32_t s_redi[kWavesPerBlock];
-    __shared__ uint32_t s_scan[kWavesPerBlock];
-    __shared__ uint32_t s_status, s_abort, s_list_n, s_npick;
-    __shared__ uint32_t s_my[W];  // this workgroup's slot payload
-
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    const int g = blockIdx.x, G = a.G;
-    IndexHeader *hdr = a.hdr;
-    if (tid == 0) {
-        s_status = hdr->build_status | hdr->sample_status;
-        s_abort = 0;
-        s_list_n = 0;
-    }
-    __syncthreads();
-    if (s_status)
-        return;
-    const uint32_t NT = hdr->n_tiles;
-    const int ntl = (NT > (uint32_t)g) ? (int)((NT - 1 - g) / G) + 1 : 0;
+    const uint32_t span = job.te - job.tb;
+    const int ntl = (span > (uint32_t)rank) ? (int)((span - 1 - rank) / G) + 1 : 0;
     const bool use_skip = !(a.flags & RFPS_F_NO_POINT_SKIP);
     const bool tele = (a.flags & RFPS_F_TELEMETRY) != 0;
-    const bool trace = (a.flags & RFPS_F_TRACE) != 0 && g == 0 && tid == 0;
+    const bool trace = record_trace && tid == 0;
 
-    // ---- LDS layout (the plan kernel checked that it fits) ----
+    // ---- LDS layout (the plan checked that it fits) ----
     unsigned long long *tkey = reinterpret_cast<unsigned long long *>(smem);
     unsigned long long *tkeyl = tkey + ntl;
     unsigned long long *bkey = tkeyl + ntl;  // [G][R+1] published local keys
@@ -133,14 +203,17 @@ __global__ __launch_bounds__(kBlock) void k_rfps_rounds(RoundArgs a)
     float *cld = ctd + G * R;  // local d2
     uint32_t *corig = reinterpret_cast<uint32_t *>(cld + G * R);
     uint32_t *picks = corig + G * R;  // candidate index g*R+h of each pick of the round
-    float *px = reinterpret_cast<float *>(picks + G * R);
+    float *pkx = reinterpret_cast<float *>(picks + kMaxRoundPicks);  // pick coordinates, in order
+    float *pky = pkx + kMaxRoundPicks;
+    float *pkz = pky + kMaxRoundPicks;
+    float *px = pkz + kMaxRoundPicks;
 
-    // ---- prologue: tile metadata, LDS offsets ----
+    // ---- prologue: tile metadata and LDS offsets (block prefix sum) ----
     const int per = (ntl + kBlock - 1) / kBlock;
     const int l0 = tid * per, l1 = min(l0 + per, ntl);
     uint32_t cnt_sum = 0;
     for (int lt = l0; lt < l1; ++lt)
-        cnt_sum += a.tcnt[g + (size_t)lt * G];
+        cnt_sum += a.tcnt[job.tb + rank + (size_t)lt * G];
     uint32_t incl = cnt_sum;
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
@@ -149,15 +222,15 @@ __global__ __launch_bounds__(kBlock) void k_rfps_rounds(RoundArgs a)
             incl += o;
     }
     if (lane == kWave - 1)
-        s_scan[wave] = incl;
+        sh.scan[wave] = incl;
     __syncthreads();
     uint32_t off = incl - cnt_sum, npl = 0;
     for (int q = 0; q < kWavesPerBlock; ++q) {
-        off += q < wave ? s_scan[q] : 0u;
-        npl += s_scan[q];
+        off += q < wave ? sh.scan[q] : 0u;
+        npl += sh.scan[q];
     }
     for (int lt = l0; lt < l1; ++lt) {
-        const size_t t = g + (size_t)lt * G;
+        const size_t t = job.tb + rank + (size_t)lt * G;
         const uint32_t c = a.tcnt[t];
         tmeta[lt] = off | (c << 16);
         tcx[lt] = a.tcx[t];
@@ -174,13 +247,13 @@ __global__ __launch_bounds__(kBlock) void k_rfps_rounds(RoundArgs a)
 
     // Seed and initial update (Sec. 3.3)
     {
-        const uint32_t p0 = a.inv[a.start];
+        const uint32_t p0 = a.inv[job.point_base + (uint32_t)job.start];
         const float sx = a.xs[p0], sy = a.ys[p0], sz = a.zs[p0];
         __syncthreads();
         for (int lt = wave; lt < ntl; lt += kWavesPerBlock) {
             const uint32_t meta = tmeta[lt];
             const uint32_t ls = meta & 0xffffu, c = meta >> 16;
-            const uint32_t gs = a.tstart[g + (size_t)lt * G];
+            const uint32_t gs = a.tstart[job.tb + rank + (size_t)lt * G];
             if ((uint32_t)lane < c) {
                 const uint32_t i = gs + lane, p = ls + lane;
                 const float x = a.xs[i], y = a.ys[i], z = a.zs[i];
@@ -188,21 +261,23 @@ __global__ __launch_bounds__(kBlock) void k_rfps_rounds(RoundArgs a)
                 py[p] = y;
                 pz[p] = z;
                 pd[p] = sqdist(x, y, z, sx, sy, sz);
-                po[p] = a.orig[i];
+                po[p] = a.orig[i] - job.point_base;
             }
             tile_rekey(lane, lt, ls, c, pd, po, trad, tkey, tbest, tthr);
+        }
+        if (tid == 0) {
+            sh.list_n = 0;
+            sh.abort = 0;
         }
         __syncthreads();
     }
 
-    unsigned long long t_tests = 0, t_pruned = 0, t_visited = 0, t_skipped = 0, t_updated = 0, t_resync = 0;
-    // phase clocks of workgroup 0 (lookahead, exchange, merge, apply)
-    const bool clocks = tele && g == 0 && tid == 0;
-    unsigned long long ph[4] = {0, 0, 0, 0}, t_mark = 0;
+    unsigned long long t_mark = 0;
     int j = 1;
     uint32_t round = 0;
-    while (j < a.m) {
+    while (j < job.m) {
         ++round;
+        ++epoch;
         if (clocks)
             t_mark = wall_clock64();
         // =============== L: local lookahead on a private copy ===============
@@ -227,50 +302,49 @@ __global__ __launch_bounds__(kBlock) void k_rfps_rounds(RoundArgs a)
             const unsigned long long wk = wave_max_u64(lk);
             const unsigned long long hit = __ballot(lk == wk && wk != 0);
             if (lane == 0) {
-                s_red[wave] = wk;
-                s_redi[wave] = hit ? (uint32_t)__builtin_amdgcn_readlane((int)lt_best, __ffsll((long long)hit) - 1)
-                                   : 0u;
+                sh.red[wave] = wk;
+                sh.redi[wave] =
+                    hit ? (uint32_t)__builtin_amdgcn_readlane((int)lt_best, __ffsll((long long)hit) - 1) : 0u;
             }
             __syncthreads();
             unsigned long long bk = 0;
             uint32_t bt = 0;
 #pragma unroll
             for (int q = 0; q < kWavesPerBlock; ++q) {
-                if (s_red[q] > bk) {
-                    bk = s_red[q];
-                    bt = s_redi[q];
+                if (sh.red[q] > bk) {
+                    bk = sh.red[q];
+                    bt = sh.redi[q];
                 }
             }
             if (s == R || bk == 0) {
-                // bound (or an empty workgroup): no more local candidates
+                // the bound (or an empty workgroup): no more local candidates
                 if (tid == 0) {
-                    s_my[6 * R] = (uint32_t)(bk >> 32);
-                    s_my[6 * R + 1] = (uint32_t)bk;
-                    for (int q = s; q < R; ++q) {
+                    sh.my[6 * R] = (uint32_t)(bk >> 32);
+                    sh.my[6 * R + 1] = (uint32_t)bk;
+                    for (int q = s; q < R; ++q)
                         for (int w = 0; w < 6; ++w)
-                            s_my[6 * q + w] = 0;
-                    }
+                            sh.my[6 * q + w] = 0;
                 }
                 break;
             }
             const uint32_t p = tbestl[bt];
             const float lx = px[p], ly = py[p], lz = pz[p];
             if (tid == 0) {
-                s_my[6 * s + 0] = __float_as_uint(lx);
-                s_my[6 * s + 1] = __float_as_uint(ly);
-                s_my[6 * s + 2] = __float_as_uint(lz);
-                s_my[6 * s + 3] = __float_as_uint(pd[p]);
-                s_my[6 * s + 4] = po[p];
-                s_my[6 * s + 5] = (uint32_t)(bk >> 32);
+                sh.my[6 * s + 0] = __float_as_uint(lx);
+                sh.my[6 * s + 1] = __float_as_uint(ly);
+                sh.my[6 * s + 2] = __float_as_uint(lz);
+                sh.my[6 * s + 3] = __float_as_uint(pd[p]);
+                sh.my[6 * s + 4] = po[p];
+                sh.my[6 * s + 5] = (uint32_t)(bk >> 32);
             }
             // local update with l_s (pruned against the local thresholds)
             for (int lt = tid; lt < ntl; lt += kBlock) {
                 const float q = sqdist(tcx[lt], tcy[lt], tcz[lt], lx, ly, lz);
                 if (!(q >= tthrl[lt]))
-                    tlist[atomicAdd(&s_list_n, 1u)] = (uint32_t)lt;
+                    tlist[atomicAdd(&sh.list_n, 1u)] = (uint32_t)lt;
             }
             __syncthreads();
-            const uint32_t nlist = s_list_n;
+            const uint32_t nlist = sh.list_n;
             for (uint32_t e = wave; e < nlist; e += kWavesPerBlock) {
                 const uint32_t lt = tlist[e];
                 const uint32_t meta = tmeta[lt];
@@ -302,31 +376,30 @@ __global__ __launch_bounds__(kBlock) void k_rfps_rounds(RoundArgs a)
             }
             __syncthreads();
             if (tid == 0)
-                s_list_n = 0;
+                sh.list_n = 0;
         }
         __syncthreads();
         if (clocks) {
             const unsigned long long t = wall_clock64();
-            ph[0] += t - t_mark;
+            tl.ph[0] += t - t_mark;
             t_mark = t;
         }
 
         // =============== X: publish and read every slot ===============
-        const uint32_t epoch = round;
         unsigned long long t_pub = trace ? wall_clock64() : 0ull;
         if (wave == 0) {
-            unsigned long long *slot = a.board + ((size_t)(epoch & 1u) * G + g) * kMaxSlotWords;
-            for (int w = lane; w < W; w += kWave)
-                if (w != W - 1)
-                    st_agent(slot + w, ((unsigned long long)epoch << 32) | s_my[w]);
+            unsigned long long *slot = board + ((size_t)(epoch & 1u) * G + rank) * kMaxSlotWords;
+            for (int w = lane; w < W - 1; w += kWave)
+                bstore<S>(slot + w, ((unsigned long long)epoch << 32) | sh.my[w]);
             if (lane == 0)
-                st_agent(slot + W - 1, ((unsigned long long)epoch << 32) | s_my[W - 1]);
+                bstore<S>(slot + W - 1, ((unsigned long long)epoch << 32) | sh.my[W - 1]);
         }
         if (tid < G) {
-            const unsigned long long *slot = a.board + ((size_t)(epoch & 1u) * G + tid) * kMaxSlotWords;
+            const unsigned long long *slot = board + ((size_t)(epoch & 1u) * G + tid) * kMaxSlotWords;
             bool ok = false;
             for (uint32_t spin = 0; spin < kSpinLimit && !ok; ++spin) {
-                const unsigned long long r = ld_agent(slot + W - 1);
+                binvalidate<S>();
+                const unsigned long long r = bload<S>(slot + W - 1);
                 if ((uint32_t)(r >> 32) == kAbortEpoch)
                     break;
                 if ((uint32_t)(r >> 32) != epoch)
@@ -335,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void k_rfps_rounds(RoundArgs a)
                 ok = true;
 #pragma unroll
                 for (int w = 0; w < W; ++w) {
-                    const unsigned long long x = ld_agent(slot + w);
+                    const unsigned long long x = bload<S>(slot + w);
                     ok &= (uint32_t)(x >> 32) == epoch;
                     v[w] = (uint32_t)x;
                 }
@@ -358,50 +431,46 @@ __global__ __launch_bounds__(kBlock) void k_rfps_rounds(RoundArgs a)
                 }
             }
             if (!ok)
-                s_abort = 1;
+                sh.abort = 1;
         }
         __syncthreads();
-        if (s_abort) {
+        if (sh.abort) {
             if (tid == 0) {
-                set_status(&hdr->sample_status, RFPS_ERR_TIMEOUT);
+                set_status(&a.hdr->sample_status, RFPS_ERR_TIMEOUT);
                 for (int par = 0; par < 2; ++par)
                     for (int w = 0; w < W; ++w)
-                        st_agent(a.board + ((size_t)par * G + g) * kMaxSlotWords + w,
-                                 (unsigned long long)kAbortEpoch << 32);
+                        bstore<S>(board + ((size_t)par * G + rank) * kMaxSlotWords + w,
+                                  (unsigned long long)kAbortEpoch << 32);
             }
-            return;
+            return false;
         }
         if (clocks) {
             const unsigned long long t = wall_clock64();
-            ph[1] += t - t_mark;
+            tl.ph[1] += t - t_mark;
             t_mark = t;
         }
 
         // =============== M: certified merge (wavefront 0) ===============
+        // Lane l tracks groups l, l+64, l+128, l+192: head index and bound key
+        // (the local key of the head candidate, or k_{R+1} once exhausted).
+        // The round's picks live in registers, pick k in lane k % 64, slot k / 64.
         if (wave == 0) {
             int hq[4];
-            float hx[4], hy[4], hz[4], ht[4], hl[4];
             unsigned long long hk[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int gg = lane + kWave * q;
-                hq[q] = R;
-                hx[q] = hy[q] = hz[q] = ht[q] = hl[q] = 0.0f;
-                hk[q] = 0ull;
-                if (gg < G) {
-                    hk[q] = bkey[gg * (R + 1)];
-                    if (hk[q] != 0ull) {
-                        hq[q] = 0;
-                        hx[q] = cx[gg * R];
-                        hy[q] = cy[gg * R];
-                        hz[q] = cz[gg * R];
-                        ht[q] = ctd[gg * R];
-                        hl[q] = cld[gg * R];
-                    }
-                }
+                hk[q] = gg < G ? bkey[gg * (R + 1)] : 0ull;
+                hq[q] = hk[q] != 0ull ? 0 : R;  // empty group: never the maximum
             }
+            float qx[kRoundPickSlots], qy[kRoundPickSlots], qz[kRoundPickSlots];
+#pragma unroll
+            for (int s = 0; s < kRoundPickSlots; ++s)
+                qx[s] = qy[s] = qz[s] = 0.0f;
+            const int pmax = min(job.m - j, kMaxRoundPicks);
             int P = 0;
-            while (j + P < a.m) {
+            while (P < pmax) {
+                // group with the largest bound (keys are unique)
                 unsigned long long lb = 0;
                 int lq = 0;
 #pragma unroll
@@ -411,98 +480,86 @@ __global__ __launch_bounds__(kBlock) void k_rfps_rounds(RoundArgs a)
                         lq = q;
                     }
                 }
-                const unsigned long long wb = wave_max_u64(lb);
-                const unsigned long long hit = __ballot(lb == wb && wb != 0ull);
+                const uint32_t mhi = wave_max_u32((uint32_t)(lb >> 32));
+                unsigned long long hit = __ballot((uint32_t)(lb >> 32) == mhi && lb != 0ull);
                 if (!hit)
                     break;
+                if (__popcll(hit) > 1) {  // equal distances: the larger low half (smaller index) wins
+                    const uint32_t mlo = wave_max_u32((uint32_t)(lb >> 32) == mhi ? (uint32_t)lb : 0u);
+                    hit = __ballot((uint32_t)(lb >> 32) == mhi && (uint32_t)lb == mlo && lb != 0ull);
+                }
                 const int L0 = __ffsll((long long)hit) - 1;
                 const int bq = __builtin_amdgcn_readlane(lq, L0);
                 int mh = R;
-                float mx = 0, my = 0, mz = 0, mt = 0, ml = 0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (q == bq) {
-                        mh = hq[q];
-                        mx = hx[q];
-                        my = hy[q];
-                        mz = hz[q];
-                        mt = ht[q];
-                        ml = hl[q];
-                    }
-                }
+                for (int q = 0; q < 4; ++q)
+                    mh = q == bq ? hq[q] : mh;
                 const int oh = __builtin_amdgcn_readlane(mh, L0);
-                const float ox = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(mx), L0));
-                const float oy = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(my), L0));
-                const float oz = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(mz), L0));
-                const float ot = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(mt), L0));
-                const float ol = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(ml), L0));
-                if (oh >= R || !(ot == ol))
-                    break;  // bound not attained: the round ends here
+                if (oh >= R)
+                    break;  // that group's next candidate is beyond its lookahead
                 const int gs = L0 + kWave * bq;
                 const int cidx = gs * R + oh;
+                const float ox = cx[cidx], oy = cy[cidx], oz = cz[cidx];
+                const float ol = cld[cidx];
+                // true distance of the head now: round-start value lowered by every pick so far
+                float t = ctd[cidx];
+#pragma unroll
+                for (int s = 0; s < kRoundPickSlots; ++s) {
+                    if (s * kWave < P && s * kWave + lane < P)
+                        t = fminf(t, sqdist(ox, oy, oz, qx[s], qy[s], qz[s]));
+                }
+                t = wave_min_dist(t);
+                if (!(t == ol))
+                    break;  // a pick of this round lowered it: the bound is not attained
+                // certified: record the selection
+                const int ps = P / kWave, pl = P % kWave;
+#pragma unroll
+                for (int s = 0; s < kRoundPickSlots; ++s) {
+                    if (s == ps && lane == pl) {
+                        qx[s] = ox;
+                        qy[s] = oy;
+                        qz[s] = oz;
+                    }
+                }
                 if (lane == 0) {
                     picks[P] = (uint32_t)cidx;
-                    ctd[cidx] = ot;  // distance at selection
+                    pkx[P] = ox;
+                    pky[P] = oy;
+                    pkz[P] = oz;
+                    ctd[cidx] = t;  // distance at selection
                 }
                 ++P;
-                // every other head loses what this pick covers
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (hq[q] < R) {
-                        const float d = sqdist(hx[q], hy[q], hz[q], ox, oy, oz);
-                        ht[q] = fminf(ht[q], d);
-                    }
-                }
-                // advance the owner's head; its true distance covers every pick so far
-                const int nh = oh + 1;
-                const unsigned long long nk = bkey[gs * (R + 1) + nh];
-                float nx = 0, ny = 0, nz = 0, nt = 0, nl = 0;
-                if (nh < R) {
-                    nx = cx[gs * R + nh];
-                    ny = cy[gs * R + nh];
-                    nz = cz[gs * R + nh];
-                    nt = ctd[gs * R + nh];
-                    nl = cld[gs * R + nh];
-                    for (int k = lane; k < P; k += kWave) {
-                        const uint32_t pc = picks[k];
-                        nt = fminf(nt, sqdist(nx, ny, nz, cx[pc], cy[pc], cz[pc]));
-                    }
-                    nt = wave_min_dist(nt);
-                }
+                // advance the owner's head
                 if (lane == L0) {
+                    const unsigned long long nk = bkey[gs * (R + 1) + oh + 1];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         if (q == bq) {
-                            hq[q] = nh;
-                            hx[q] = nx;
-                            hy[q] = ny;
-                            hz[q] = nz;
-                            ht[q] = nt;
-                            hl[q] = nl;
+                            hq[q] = oh + 1;
                             hk[q] = nk;
                         }
                     }
                 }
             }
             if (lane == 0)
-                s_npick = (uint32_t)P;
-            if (g == 0) {
+                sh.npick = (uint32_t)P;
+            if (rank == 0) {
                 for (int k = lane; k < P; k += kWave) {
                     const uint32_t pc = picks[k];
-                    a.out_idx[j + k] = (int32_t)corig[pc];
-                    if (a.out_d2)
-                        a.out_d2[j + k] = ctd[pc];
+                    job.out_idx[j + k] = (int32_t)corig[pc];
+                    if (job.out_d2)
+                        job.out_d2[j + k] = ctd[pc];
                 }
             }
         }
         __syncthreads();
-        const int P = (int)s_npick;
+        const int P = (int)sh.npick;
         if (P == 0) {
             // impossible by construction (the largest bound is attained at round
             // start); kept as a guard so a violated invariant cannot spin forever
             if (tid == 0)
-                set_status(&hdr->sample_status, RFPS_ERR_INTERNAL);
-            return;
+                set_status(&a.hdr->sample_status, RFPS_ERR_INTERNAL);
+            return false;
         }
         if (trace && round - 1 < (uint32_t)kTraceCap) {
             a.trace[2 * (size_t)(round - 1)] = t_pub;
@@ -510,11 +567,11 @@ __global__ __launch_bounds__(kBlock) void k_rfps_rounds(RoundArgs a)
         }
         if (clocks) {
             const unsigned long long t = wall_clock64();
-            ph[2] += t - t_mark;
+            tl.ph[2] += t - t_mark;
             t_mark = t;
         }
         j += P;
-        if (j >= a.m)
+        if (j >= job.m)
             break;
 
         // =============== A: apply the round's picks to the true state ===============
@@ -523,18 +580,19 @@ __global__ __launch_bounds__(kBlock) void k_rfps_rounds(RoundArgs a)
             const float ccx = tcx[lt], ccy = tcy[lt], ccz = tcz[lt];
             int k = 0;
             for (; k < P; ++k) {
-                const uint32_t pc = picks[k];
-                const float q = sqdist(ccx, ccy, ccz, cx[pc], cy[pc], cz[pc]);
+                const float q = sqdist(ccx, ccy, ccz, pkx[k], pky[k], pkz[k]);
                 if (!(q >= thr))
                     break;
             }
-            t_tests += (k < P) ? (unsigned long long)(k + 1) : (unsigned long long)P;
-            t_pruned += (unsigned long long)k;
+            if (tele) {
+                tl.tests += (k < P) ? (unsigned long long)(k + 1) : (unsigned long long)P;
+                tl.pruned += (unsigned long long)k;
+            }
             if (k < P)
-                tlist[atomicAdd(&s_list_n, 1u)] = (uint32_t)lt | ((uint32_t)k << 20);
+                tlist[atomicAdd(&sh.list_n, 1u)] = (uint32_t)lt | ((uint32_t)k << 20);
         }
         __syncthreads();
-        const uint32_t nlist = s_list_n;
+        const uint32_t nlist = sh.list_n;
         for (uint32_t e = wave; e < nlist; e += kWavesPerBlock) {
             const uint32_t lt = tlist[e] & 0xfffffu;
             const int k0 = (int)(tlist[e] >> 20);
@@ -548,13 +606,12 @@ __global__ __launch_bounds__(kBlock) void k_rfps_rounds(RoundArgs a)
             float d = pd[pp];
             bool changed = false;
             for (int k = k0; k < P; ++k) {
-                const uint32_t pc = picks[k];
-                const float sx = cx[pc], sy = cy[pc], sz = cz[pc];
+                const float sx = pkx[k], sy = pky[k], sz = pkz[k];
                 if (k > k0 && sqdist(ccx, ccy, ccz, sx, sy, sz) >= thr)
                     continue;  // uniform across the wave
                 if (tele && lane == 0) {
-                    t_visited += cnt;
-                    t_tests += (k > k0);
+                    tl.visited += cnt;
+                    tl.tests += (k > k0);
                 }
                 if (valid) {
                     const float dx = x - sx, dy = y - sy, dz = z - sz;
@@ -566,80 +623,239 @@ __global__ __launch_bounds__(kBlock) void k_rfps_rounds(RoundArgs a)
                         d = t;
                         changed = true;
                     }
-                    t_skipped += skip;
+                    if (tele)
+                        tl.skipped += skip;
                 }
             }
             if (changed)
                 pd[pp] = d;
             const unsigned long long um = __ballot(changed);
             if (tele && lane == 0) {
-                t_updated += (unsigned long long)__popcll(um);
-                t_resync += um != 0;
+                tl.updated += (unsigned long long)__popcll(um);
+                tl.resync += um != 0;
             }
             if (um)
                 tile_rekey(lane, lt, ls, cnt, pd, po, trad, tkey, tbest, tthr);
         }
         __syncthreads();
         if (tid == 0)
-            s_list_n = 0;
+            sh.list_n = 0;
         if (clocks)
-            ph[3] += wall_clock64() - t_mark;
+            tl.ph[3] += wall_clock64() - t_mark;
     }
+    tl.rounds += round;
+    __syncthreads();  // LDS is reused by the next cloud
+    return true;
+}
 
-    if (clocks) {
+// Adds the per-thread telemetry of a workgroup to the header counters.
+__device__ void flush_telemetry(IndexHeader *hdr, const RoundTele &tl, bool clocks)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const unsigned long long v[6] = {tl.tests, tl.pruned, tl.visited, tl.skipped, tl.updated, tl.resync};
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        unsigned long long s = v[q];
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1)
+            s += __shfl_xor(s, o, kWave);
+        if (lane == 0 && s)
+            atomicAdd(&hdr->tele[2 + q], s);
+    }
+    if (clocks)
         for (int q = 0; q < 4; ++q)
-            atomicAdd(&hdr->tele[kTeleTicksLookahead + q], ph[q]);
-    }
-    if (tele) {
-        unsigned long long v[6] = {t_tests, t_pruned, t_visited, t_skipped, t_updated, t_resync};
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            unsigned long long s = v[q];
-#pragma unroll
-            for (int o = kWave / 2; o > 0; o >>= 1)
-                s += __shfl_xor(s, o, kWave);
-            if (lane == 0 && s)
-                atomicAdd(&hdr->tele[2 + q], s);
-        }
-        if (g == 0 && tid == 0) {
+            atomicAdd(&hdr->tele[kTeleTicksLookahead + q], tl.ph[q]);
+}
+
+// ---------------------------------------------------------------------------
+// Single cloud: one team made of the whole grid, agent-scope exchange.
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_rfps_rounds(RoundArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ RoundShared sh;
+    __shared__ uint32_t s_status;
+    const int tid = threadIdx.x;
+    IndexHeader *hdr = a.hdr;
+    if (tid == 0)
+        s_status = hdr->build_status | hdr->sample_status;
+    __syncthreads();
+    if (s_status)
+        return;
+    const bool tele = (a.flags & RFPS_F_TELEMETRY) != 0;
+    const bool clocks = tele && blockIdx.x == 0 && tid == 0;
+    CloudJob job;
+    job.tb = 0;
+    job.te = hdr->n_tiles;
+    job.point_base = 0;
+    job.m = a.m;
+    job.start = a.start;
+    job.out_idx = a.out_idx;
+    job.out_d2 = a.out_d2;
+    uint32_t epoch = 0;
+    RoundTele tl;
+    const bool ok = sample_cloud<R, Scope::Agent>(a, job, blockIdx.x, a.G, a.board, epoch, smem, sh, tl,
+                                                  (a.flags & RFPS_F_TRACE) != 0 && blockIdx.x == 0, clocks);
+    if (tele && ok) {
+        flush_telemetry(hdr, tl, clocks);
+        if (blockIdx.x == 0 && tid == 0) {
             atomicAdd(&hdr->tele[0], (unsigned long long)(a.m > 1 ? a.m - 2 : 0));
-            atomicAdd(&hdr->tele[1], (unsigned long long)NT);
-            atomicAdd(&hdr->tele[8], (unsigned long long)round);
+            atomicAdd(&hdr->tele[1], (unsigned long long)hdr->n_tiles);
+            atomicAdd(&hdr->tele[kTeleExchanges], tl.rounds);
         }
     }
-    if (g == 0 && tid == 0)
-        hdr->trace_n = round;
+    if (blockIdx.x == 0 && tid == 0)
+        hdr->trace_n = (uint32_t)tl.rounds;
 }
 
 template __global__ void k_rfps_rounds<2>(RoundArgs);
 template __global__ void k_rfps_rounds<4>(RoundArgs);
 template __global__ void k_rfps_rounds<8>(RoundArgs);
 
-size_t rfps_rounds_static_lds(int R)
+// ---------------------------------------------------------------------------
+// Batches: teams of T workgroups, all on one XCD (found from the hardware
+// XCC id at run time), exchange through that XCD's L2; every team takes the
+// next cloud from a queue ordered by decreasing cost until it is empty.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t xcc_id()
 {
-    const void *fn = R == 2   ? reinterpret_cast<const void *>(k_rfps_rounds<2>)
-                     : R == 4 ? reinterpret_cast<const void *>(k_rfps_rounds<4>)
-                     : R == 8 ? reinterpret_cast<const void *>(k_rfps_rounds<8>)
-                              : nullptr;
-    hipFuncAttributes attr;
-    if (!fn || hipFuncGetAttributes(&attr, fn) != hipSuccess)
-        return 0;
-    return attr.sharedSizeBytes;
+    return __builtin_amdgcn_s_getreg((20) | (0 << 6) | ((16 - 1) << 11)) & 0xffu;
 }
 
-hipError_t launch_rfps_rounds(const IndexView &v, int m, int start, const SampleLaunch &L, int32_t *out_idx,
-                              float *out_d2, hipStream_t s)
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_rfps_rounds_batched(RoundArgs a)
 {
-    k_rounds_plan<<<(L.G + kBlock - 1) / kBlock, kBlock, 0, s>>>(v.hdr, v.tcnt, L.G, L.R, L.lds_budget);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || m <= 1)
-        return e;
-    const void *fn = L.R == 2   ? reinterpret_cast<const void *>(k_rfps_rounds<2>)
-                     : L.R == 4 ? reinterpret_cast<const void *>(k_rfps_rounds<4>)
-                     : L.R == 8 ? reinterpret_cast<const void *>(k_rfps_rounds<8>)
-                                : nullptr;
-    if (!fn)
-        return hipErrorInvalidValue;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ RoundShared sh;
+    __shared__ uint32_t s_status, s_xcc, s_xrank, s_cloud, s_ok;
+    const int tid = threadIdx.x;
+    IndexHeader *hdr = a.hdr;
+    const BatchCtl &bc = a.bc;
+    BatchState *st = a.bstate;
+    if (tid == 0) {
+        s_status = hdr->build_status | hdr->sample_status;
+        s_ok = 0;
+        if (!s_status) {
+            // join the workgroups of this XCD, then wait until all have joined
+            const uint32_t x = xcc_id();
+            s_xcc = x;
+            s_xrank = x < kMaxXcds ? atomicAdd(&st->xcd_count[x], 1u) : 0xffffffffu;
+            atomicAdd(&st->joined, 1u);
+            uint32_t spin = 0;
+            while (__hip_atomic_load(&st->joined, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x &&
+                   ++spin < kSpinLimit) {
+            }
+            if (spin >= kSpinLimit || x >= kMaxXcds) {
+                set_status(&hdr->sample_status, RFPS_ERR_TIMEOUT);
+            } else if (__hip_atomic_load(&st->xcd_count[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
+                       (uint32_t)bc.per_xcd) {
+                // the teams assume per_xcd workgroups on every XCD
+                set_status(&hdr->sample_status, RFPS_ERR_UNSUPPORTED);
+            } else {
+                s_ok = 1;
+            }
+        }
+    }
+    __syncthreads();
+    if (s_status || !s_ok)
+        return;
+    const int T = bc.team_size;
+    const int team = (int)s_xcc * (bc.per_xcd / T) + (int)s_xrank / T;
+    const int rank = (int)s_xrank % T;
+    unsigned long long *board = a.board + (size_t)team * (2 * T + 1) * kMaxSlotWords;
+    unsigned long long *ctl = board + (size_t)2 * T * kMaxSlotWords;  // the team's control slot
+    const bool tele = (a.flags & RFPS_F_TELEMETRY) != 0;
+    RoundTele tl;
+    uint32_t epoch = 0, turn = 0;
+    for (;;) {
+        // The team leader takes the next cloud that needs an exchange and
+        // posts it.  Every posted cloud costs at least one exchange, which the
+        // leader cannot finish before every member has read the post, so a
+        // post is never overwritten unread.
+        ++turn;
+        if (tid == 0) {
+            if (rank == 0) {
+                uint32_t q;
+                do {
+                    q = atomicAdd(&st->next, 1u);
+                } while (q < (uint32_t)bc.batch && bc.m[a.order[q]] < 2);
+                bstore<Scope::Xcd>(ctl, ((unsigned long long)turn << 32) | q);
+                s_cloud = q;
+            } else {
+                uint32_t spin = 0;
+                unsigned long long v = 0;
+                for (; spin < kSpinLimit; ++spin) {
+                    binvalidate<Scope::Xcd>();
+                    v = bload<Scope::Xcd>(ctl);
+                    if ((uint32_t)(v >> 32) == turn)
+                        break;
+                }
+                s_cloud = spin < kSpinLimit ? (uint32_t)v : 0xffffffffu;
+                if (spin >= kSpinLimit)
+                    set_status(&hdr->sample_status, RFPS_ERR_TIMEOUT);
+            }
+        }
+        __syncthreads();
+        const uint32_t q = s_cloud;
+        __syncthreads();
+        if (q >= (uint32_t)bc.batch)
+            break;
+        const int c = a.order[q];
+        CloudJob job;
+        job.tb = a.tile_first[c];
+        job.te = a.tile_first[c + 1];
+        job.point_base = (uint32_t)bc.offsets[c];
+        job.m = bc.m[c];
+        job.start = bc.starts ? bc.starts[c] : 0;
+        job.out_idx = a.out_idx + bc.out_offsets[c];
+        job.out_d2 = a.out_d2 ? a.out_d2 + bc.out_offsets[c] : nullptr;
+        if (!sample_cloud<R, Scope::Xcd>(a, job, rank, T, board, epoch, smem, sh, tl, false, false))
+            return;
+    }
+    if (tele) {
+        flush_telemetry(hdr, tl, false);
+        if (rank == 0 && tid == 0)
+            atomicAdd(&hdr->tele[kTeleExchanges], tl.rounds);
+    }
+}
+
+template __global__ void k_rfps_rounds_batched<2>(RoundArgs);
+template __global__ void k_rfps_rounds_batched<4>(RoundArgs);
+template __global__ void k_rfps_rounds_batched<8>(RoundArgs);
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+static const void *rounds_fn(int R, bool batched)
+{
+    if (batched)
+        return R == 2   ? reinterpret_cast<const void *>(k_rfps_rounds_batched<2>)
+               : R == 4 ? reinterpret_cast<const void *>(k_rfps_rounds_batched<4>)
+               : R == 8 ? reinterpret_cast<const void *>(k_rfps_rounds_batched<8>)
+                        : nullptr;
+    return R == 2   ? reinterpret_cast<const void *>(k_rfps_rounds<2>)
+           : R == 4 ? reinterpret_cast<const void *>(k_rfps_rounds<4>)
+           : R == 8 ? reinterpret_cast<const void *>(k_rfps_rounds<8>)
+                    : nullptr;
+}
+
+size_t rfps_rounds_static_lds(int R)
+{
+    size_t mx = 0;
+    for (int b = 0; b < 2; ++b) {
+        const void *fn = rounds_fn(R, b == 1);
+        hipFuncAttributes attr;
+        if (!fn || hipFuncGetAttributes(&attr, fn) != hipSuccess)
+            return 0;
+        mx = attr.sharedSizeBytes > mx ? attr.sharedSizeBytes : mx;
+    }
+    return mx;
+}
+
+static RoundArgs round_args(const IndexView &v, int m, int start, const SampleLaunch &L, int32_t *out_idx,
+                            float *out_d2)
+{
     RoundArgs a;
     a.hdr = v.hdr;
     a.xs = v.xs;
@@ -663,11 +879,88 @@ hipError_t launch_rfps_rounds(const IndexView &v, int m, int start, const Sample
     a.G = L.G;
     a.flags = L.flags;
     a.lds_budget = L.lds_budget;
+    a.bc = BatchCtl{};
+    a.bstate = nullptr;
+    a.tile_first = nullptr;
+    a.order = nullptr;
+    return a;
+}
+
+hipError_t launch_rfps_rounds(const IndexView &v, int m, int start, const SampleLaunch &L, int32_t *out_idx,
+                              float *out_d2, hipStream_t s)
+{
+    k_rounds_plan<<<(L.G + kBlock - 1) / kBlock, kBlock, 0, s>>>(v.hdr, v.tcnt, L.G, L.R, L.lds_budget);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || m <= 1)
+        return e;
+    const void *fn = rounds_fn(L.R, false);
+    if (!fn)
+        return hipErrorInvalidValue;
+    RoundArgs a = round_args(v, m, start, L, out_idx, out_d2);
     void *args[] = {&a};
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_budget);
     if (e != hipSuccess)
         return e;
-    return hipLaunchCooperativeKernel(fn, dim3(L.G), dim3(kBlock), args, L.lds_budget, s);
+    return launch_persistent(fn, L.G, args, L.lds_budget, s);
+}
+
+// Batched: per-cloud capacity check for teams of bc.team_size workgroups,
+// then the first output of every cloud (its start, at distance +inf) and the
+// counters the sampler does not keep.
+__global__ __launch_bounds__(kBlock) void k_batch_plan(IndexHeader *hdr, const uint32_t *__restrict__ tcnt,
+                                                       BatchCtl bc, const uint32_t *__restrict__ tile_first, int R,
+                                                       uint32_t budget, int32_t *out_idx, float *out_d2)
+{
+    if (hdr->build_status)
+        return;
+    const int T = bc.team_size;
+    const int total = bc.batch * T;
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x, nth = gridDim.x * blockDim.x;
+    for (int w = tid; w < total; w += nth) {
+        const int c = w / T, r = w % T;
+        if (!team_fits(tcnt, tile_first[c], tile_first[c + 1], T, R, budget, r))
+            set_status(&hdr->sample_status, RFPS_ERR_CAPACITY);
+    }
+    for (int c = tid; c < bc.batch; c += nth) {
+        const uint32_t o = bc.out_offsets[c];
+        out_idx[o] = bc.starts ? bc.starts[c] : 0;
+        if (out_d2)
+            out_d2[o] = INFINITY;
+    }
+    if (tid == 0) {
+        unsigned long long it = 0;
+        for (int c = 0; c < bc.batch; ++c)
+            it += bc.m[c] > 2 ? (unsigned long long)(bc.m[c] - 2) : 0ull;
+        hdr->tele[0] = it;
+        hdr->tele[1] = hdr->n_tiles;
+    }
+}
+
+hipError_t launch_rfps_rounds_batched(const IndexView &v, const SampleLaunch &L, int32_t *out_idx,
+                                      float *out_d2, hipStream_t s)
+{
+    const int total = v.bc.batch * v.bc.team_size;
+    k_batch_plan<<<std::min((total + kBlock - 1) / kBlock, 1024), kBlock, 0, s>>>(
+        v.hdr, v.tcnt, v.bc, v.tile_first, L.R, L.lds_budget, out_idx, out_d2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const void *fn = rounds_fn(L.R, true);
+    if (!fn)
+        return hipErrorInvalidValue;
+    RoundArgs a = round_args(v, 0, 0, L, out_idx, out_d2);
+    a.bc = v.bc;
+    a.bstate = v.bstate;
+    a.tile_first = v.tile_first;
+    a.order = v.order;
+    void *args[] = {&a};
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_budget);
+    if (e != hipSuccess)
+        return e;
+    e = launch_persistent(fn, L.G, args, L.lds_budget, s);
+    if (e != hipSuccess)
+        return e;
+    return launch_sample_finalize(v.hdr, v.bc.m_total, out_idx, out_d2, s);
 }
 
 }  // namespace rfps

@@ -7,13 +7,16 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "rfps.h")
+HEADERS = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if f.endswith(".h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(rfps_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(rfps_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -24,7 +27,7 @@ def L():
 
 def test_every_declared_symbol_is_exported(L):
     names = declared_functions()
-    assert len(names) >= 12
+    assert len(names) >= 27 and "rfps_mlp_train_step" in names and "rfps_sample_batched" in names
     for name in names:
         assert hasattr(L, name), name
 
@@ -81,6 +84,10 @@ def test_invalid_arguments_return_before_device_work(L):
     out = ctypes.c_void_p(0x2000)
     assert L.rfps_sample(None, 1, 0, None, out, None, None) == 1
     h.n, h.n_vox, h.tile, h.ws, h.ws_bytes = 100, 16, 64, 0x1000, 1 << 30
+    assert L.rfps_sample(ctypes.byref(h), 10, 0, None, out, None, None) == 1   # shells = 0 is no handle
+    h.shells = 65
+    assert L.rfps_sample(ctypes.byref(h), 10, 0, None, out, None, None) == 1
+    h.shells = 1
     assert L.rfps_sample(ctypes.byref(h), 0, 0, None, out, None, None) == 1
     assert L.rfps_sample(ctypes.byref(h), 101, 0, None, out, None, None) == 1
     assert L.rfps_sample(ctypes.byref(h), 10, 100, None, out, None, None) == 1
@@ -104,3 +111,89 @@ def test_invalid_arguments_return_before_device_work(L):
     assert L.rfps_read_telemetry(None, None, ctypes.byref(t)) == 1
     assert L.rfps_read_status(None, None) == 1
     assert L.rfps_read_trace(None, None, out, 4, None) == -1
+
+
+def test_batched_workspace_and_host_checks(L):
+    import paper_2606_06255_amd as rf
+    p = rf.rfps_params()
+    a = L.rfps_batched_workspace_size(100000, 32, ctypes.byref(p))
+    single = L.rfps_index_workspace_size(100000, ctypes.byref(rf.rfps_params(n_vox=64)))
+    assert a > 0 and a % 256 == 0 and a >= single
+    fixed = rf.rfps_params(n_vox=16)
+    assert 0 < L.rfps_batched_workspace_size(100000, 32, ctypes.byref(fixed)) <= a
+    assert L.rfps_batched_workspace_size(100000, 0, None) == 0
+    assert L.rfps_batched_workspace_size(100000, 4097, None) == 0
+    assert L.rfps_batched_workspace_size(10, 11, None) == 0
+    assert L.rfps_batched_workspace_size(0, 1, None) == 0
+    assert L.rfps_batched_workspace_size(1000, 2, ctypes.byref(rf.rfps_params(lookahead=3))) == 0
+    fake = ctypes.c_void_p(0x1000)
+    out = ctypes.c_void_p(0x2000)
+    args = dict(xyz=fake, n=100, off=fake, m=fake, st=None, b=4, mt=20, p=None, ws=fake, wsb=1 << 30, oi=out)
+
+    def call(**kw):
+        a = dict(args)
+        a.update(kw)
+        return L.rfps_sample_batched(a["xyz"], a["n"], a["off"], a["m"], a["st"], a["b"], a["mt"], a["p"],
+                                     a["ws"], a["wsb"], a["oi"], None, None)
+    assert call(xyz=None) == 1
+    assert call(off=None) == 1
+    assert call(m=None) == 1
+    assert call(oi=None) == 1
+    assert call(b=0) == 1
+    assert call(b=101) == 1
+    assert call(mt=3) == 1        # fewer outputs than clouds
+    assert call(mt=101) == 1      # more outputs than points
+    assert call(n=0) == 1
+    for fl in (rf.F_NO_PRUNE, rf.F_SINGLE_PICK, rf.F_TRACE):
+        assert call(p=ctypes.byref(rf.rfps_params(flags=fl))) == 5
+    assert call(ws=None) == 3
+    assert call(ws=ctypes.c_void_p(0x1001)) == 3
+    assert call(wsb=64) == 3
+    assert L.rfps_batched_read_status(None, 0, None) == 3
+    t = rf.rfps_telemetry()
+    assert L.rfps_batched_read_telemetry(fake, 1 << 20, None, None) == 1
+    best = rf.rfps_params()
+    assert L.rfps_autotune_batched(fake, 100, fake, fake, None, 4, 20, None, 0, fake, 1 << 30, out, None, None,
+                                   ctypes.byref(best), None) == 1
+    assert L.rfps_autotune_batched(fake, 100, fake, fake, None, 4, 20, None, 3, fake, 1 << 30, out, None, None,
+                                   None, None) == 1
+
+
+def test_shell_parameter(L):
+    import paper_2606_06255_amd as rf
+    base = L.rfps_index_workspace_size(5000, ctypes.byref(rf.rfps_params(n_vox=16)))
+    for sh in (5.0, 0.25, float("inf")):
+        assert L.rfps_index_workspace_size(5000, ctypes.byref(rf.rfps_params(n_vox=16, shell_spacing=sh))) >= base
+    for bad in (-1.0, float("nan")):
+        assert L.rfps_index_workspace_size(5000, ctypes.byref(rf.rfps_params(n_vox=16, shell_spacing=bad))) == 0
+    fake = ctypes.c_void_p(0x1000)
+    h = rf.rfps_index()
+    p = rf.rfps_params(n_vox=16, shell_spacing=-2.0)
+    assert L.rfps_build_index(fake, 10, ctypes.byref(p), fake, 1 << 30, None, ctypes.byref(h)) == 1
+
+
+def test_mlp_host_checks(L):
+    import paper_2606_06255_amd as rf
+    assert rf.mlp_candidate(0) == (8, 0.0) and rf.mlp_candidate(35) == (128, 20.0)
+    assert rf.mlp_candidate(13) == (24, 5.0)
+    with pytest.raises(ValueError):
+        rf.mlp_candidate(36)
+    assert L.rfps_mlp_state_size() >= 4 * 3 * rf.MLP_PARAMS
+    assert L.rfps_mlp_workspace_size(0) == 0 and L.rfps_mlp_workspace_size(1 << 17) == 0
+    assert L.rfps_mlp_workspace_size(64) > L.rfps_mlp_workspace_size(1) > 0
+    fake = ctypes.c_void_p(0x1000)
+    big = 1 << 30
+    # state / workspace checks come before any device work
+    assert L.rfps_mlp_forward(None, big, fake, 1, fake, big, fake, None) == 3
+    assert L.rfps_mlp_forward(fake, 16, fake, 1, fake, big, fake, None) == 3
+    assert L.rfps_mlp_forward(fake, big, fake, 0, fake, big, fake, None) == 1
+    assert L.rfps_mlp_forward(fake, big, fake, 4, fake, 64, fake, None) == 3
+    assert L.rfps_mlp_forward(fake, big, None, 1, fake, big, fake, None) == 1
+    assert L.rfps_mlp_train_step(fake, big, fake, fake, None, 4, 0.0, fake, big, None, None) == 1
+    assert L.rfps_mlp_train_step(fake, big, fake, fake, None, 4, float("nan"), fake, big, None, None) == 1
+    assert L.rfps_mlp_choose(fake, big, fake, 36, 0.0, fake, big, fake, None, None) == 1
+    assert L.rfps_mlp_choose(fake, big, fake, 3, -1.0, fake, big, fake, None, None) == 1
+    assert L.rfps_mlp_features(None, 10, fake, big, fake, None) == 1
+    assert L.rfps_mlp_features(fake, 0, fake, big, fake, None) == 1
+    assert L.rfps_mlp_load(fake, big, None, None) == 1
+    assert L.rfps_mlp_save(None, big, fake, None) == 3

@@ -110,6 +110,28 @@ def test_room_full(oracle_lib):
     assert_same(m.fps_plain(x, 20000, 0, variant=0), ref, "plain persistent")
 
 
+def test_range_shells(oracle_lib):
+    # range shells only change the partition: the result must not move
+    m = rf()
+    cases = ((synth.cube(2), 1024, (0.05, 0.3)), (synth.room(0), 20000, (1.0, 3.0)),
+             (synth.lidar(1), 28656, (5.0, 20.0)))
+    for P, M, spacings in cases:
+        ref = oracle_lib.fps(P, M, 0, threads=0)
+        x = dev(P)
+        for sh in spacings:
+            for n_vox in (8, 32, 128):
+                idx = m.build_index(x, n_vox=n_vox, shell=sh)
+                assert idx.handle.shells > 1
+                got = m.sample(idx, M, 0)
+                assert m.read_status(idx) == 0
+                assert_same(got, ref, "N=%d shell=%g n_vox=%d" % (P.shape[0], sh, n_vox))
+    # shells of growing cells coarsen the sparse far range of a spinning sensor
+    P = synth.lidar(1)
+    flat = m.read_index_info(m.build_index(dev(P), n_vox=96))["n_tiles"]
+    shelled = m.read_index_info(m.build_index(dev(P), n_vox=96, shell=10.0))["n_tiles"]
+    assert shelled < flat
+
+
 def test_lidar_multistage(oracle_lib):
     m = rf()
     P = synth.lidar(0)
