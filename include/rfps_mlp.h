@@ -3,8 +3,8 @@
  *
  * The paper chooses the voxel resolution v (n_vox of eq. voxel_size) by
  * hand and reports that the best value depends on the cloud (Sec. 5.6.2).
- * This small network predicts, from 516 features of a cloud, the run time
- * (log ms) and the pruning rate of RadiusFPS-G for each of 36 candidate
+ * This small network predicts, from 516 features of a cloud, the relative
+ * run time and the pruning rate of RadiusFPS-G for each of 36 candidate
  * (n_vox, shell spacing) pairs, so that a cloud can be indexed with the
  * candidate it expects to be fastest.  The choice never changes the
  * sampled sequence (every partition of a cloud into voxels and tiles gives
@@ -18,8 +18,10 @@
  *
  * Parameters are packed in this order, each matrix row-major [out][in]:
  *   W1 [64][516], b1 [64], W2 [64][64], b2 [64], W3 [72][64], b3 [72]
- * (41,928 values).  Outputs: y[k] = predicted ln(ms) of candidate k,
- * y[36 + k] = its predicted pruning rate (fraction of point visits saved).
+ * (41,928 values).  Outputs: y[k] = predicted ln of the run time (index
+ * build + sampling) of candidate k minus the mean of that log over the 36
+ * candidates (only the ranking matters), y[36 + k] = its predicted pruning
+ * rate (fraction of point visits saved).
  *
  * Features of a cloud of N points (float32): f[0] = (ln N - 11) / 2;
  * f[1..3] = ln(1 + E_a) / 2 with E_a the bounding-box extents; f[4 + c] =
@@ -48,7 +50,7 @@ extern "C" {
 #define RFPS_MLP_CANDIDATES 36
 #define RFPS_MLP_PARAMS 41928
 
-/* Candidate k (0..35): n_vox = {8,12,16,24,32,48,64,96,128}[k / 4], shell
+/* Candidate k (0..35): n_vox = {12,16,24,32,48,64,96,128,192}[k / 4], shell
  * spacing = {0 (one shell), 5, 10, 20}[k % 4].  Returns 0, or 1 for a bad k. */
 int32_t rfps_mlp_candidate(int32_t k, int32_t *n_vox, float *shell_spacing);
 
@@ -91,7 +93,7 @@ rfps_status rfps_mlp_train_step(void *state, size_t state_bytes, const float *x,
                                 const float *w, int32_t batch, float lr, void *ws, size_t ws_bytes,
                                 float *loss, void *stream);
 
-/* Choice for one cloud: the candidate with the lowest predicted ln(ms),
+/* Choice for one cloud: the candidate with the lowest predicted log time,
  * kept only if it beats the prediction for default_cand by more than
  * margin, else default_cand.  feat: device [516] (rfps_mlp_features);
  * choice: device int32; y: device [72] predictions or NULL. */

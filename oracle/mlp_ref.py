@@ -22,7 +22,7 @@ from __future__ import annotations
 import numpy as np
 
 F_IN, H1, H2 = 516, 64, 64
-N_VOX_CAND = (8, 12, 16, 24, 32, 48, 64, 96, 128)
+N_VOX_CAND = (12, 16, 24, 32, 48, 64, 96, 128, 192)
 SHELL_CAND = (0.0, 5.0, 10.0, 20.0)        # 0 = one shell (the uniform grid)
 N_CAND = len(N_VOX_CAND) * len(SHELL_CAND)  # 36
 OUT = 2 * N_CAND                            # log-ms and pruning rate per candidate

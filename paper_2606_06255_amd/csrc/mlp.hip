@@ -3,8 +3,8 @@
 //
 // The network maps 516 features of a cloud (log N, the bounding-box extents
 // and the 8^3 occupancy histogram) through two hidden layers of 64 ReLU
-// units to 72 outputs: a predicted log run time and a pruning rate for each
-// of 36 candidate (n_vox, shell spacing) pairs.  Weight matrices are used in
+// units to 72 outputs: a predicted relative log run time and a pruning rate
+// for each of 36 candidate (n_vox, shell spacing) pairs.  Weight matrices are used in
 // bfloat16 (round to nearest even of an FP32 master copy); biases,
 // activations, accumulation and the optimiser state are FP32.  Whatever the
 // network picks, the sampled sequence is the same (every partition is
@@ -35,7 +35,7 @@ constexpr float kBeta1 = 0.9f, kBeta2 = 0.999f, kEps = 1e-8f;
 constexpr int kMaxRows = 1 << 16;  // rows of one forward or training call
 
 // Candidate table: n_vox major, shell spacing minor (0 = one shell).
-constexpr int kNVox[9] = {8, 12, 16, 24, 32, 48, 64, 96, 128};
+constexpr int kNVox[9] = {12, 16, 24, 32, 48, 64, 96, 128, 192};
 constexpr float kShell[4] = {0.0f, 5.0f, 10.0f, 20.0f};
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));

@@ -1,0 +1,256 @@
+"""Voxel-parameter choice for RadiusFPS-G: the default rule and the trained network.
+
+The paper sets the voxel resolution by hand and finds that the best value
+depends on the cloud (Sec. 5.6.2).  Here a small network (include/rfps_mlp.h)
+predicts, from 516 features of a cloud, how fast each of 36 candidate
+(n_vox, shell spacing) pairs would run, and the cloud is indexed with the
+predicted fastest one -- unless it is not predicted to beat the library's
+default rule by a margin, in which case the default is kept.  No choice can
+change the sampled sequence; it only changes the speed.
+
+Everything on the GPU runs in librfps kernels: features, forward pass,
+choice, and in training the gradient and Adam steps.  This module only
+moves data and keeps the bookkeeping.
+
+Training workflow (needs a GPU):
+    python -m paper_2606_06255_amd.param_model --out DIR
+generates clouds (half room-like, half LiDAR-like, N log-uniform in
+[8000, 1048576], M = N // 4), times build + sample for every candidate on
+every cloud (the sweep), trains the network on the training clouds and
+evaluates its choices on held-out clouds and on the dense 1M-point LiDAR-like
+cloud against the default rule and the best candidate of the sweep.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import (MLP, MLP_CANDIDATES, MLP_INPUTS, MLP_OUTPUTS, MLP_PARAMS, F_TELEMETRY, build_index,
+               default_n_vox, mlp_candidate, read_status, read_telemetry, sample)
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+MODEL_PATH = os.path.join(_PKG, "param_mlp.npz")
+SHAPES = (("W1", (64, MLP_INPUTS)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (MLP_OUTPUTS, 64)),
+          ("b3", (MLP_OUTPUTS,)))
+
+
+def candidates():
+    return [mlp_candidate(k) for k in range(MLP_CANDIDATES)]
+
+
+def default_candidate(n: int) -> int:
+    """Candidate index of the library's default rule (its n_vox, one shell)."""
+    nv = default_n_vox(n)
+    for k, (cn, sh) in enumerate(candidates()):
+        if cn == nv and sh == 0.0:
+            return k
+    raise ValueError("default n_vox %d is not a candidate" % nv)
+
+
+def init_params(seed: int) -> np.ndarray:
+    """He-uniform weights, zero biases (packed in the library's order)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shape in SHAPES:
+        if name.startswith("W"):
+            parts.append(rng.uniform(-1.0, 1.0, int(np.prod(shape))) * math.sqrt(6.0 / shape[1]))
+        else:
+            parts.append(np.zeros(int(np.prod(shape))))
+    return np.concatenate(parts).astype(np.float32)
+
+
+class ParamModel:
+    """The trained network (weights from param_mlp.npz) on one device."""
+
+    def __init__(self, device, path: str = MODEL_PATH, margin: float | None = None):
+        data = np.load(path, allow_pickle=False)
+        self.net = MLP(device)
+        self.net.load(data["params"])
+        self.margin = float(data["margin"]) if margin is None else float(margin)
+        self.device = device
+        self.feat = torch.empty(MLP_INPUTS, dtype=torch.float32, device=device)
+
+    def choose(self, xyz: torch.Tensor):
+        """(n_vox, shell spacing, candidate, predictions): waits for the device."""
+        n = xyz.shape[0]
+        self.net.features(xyz, out=self.feat)
+        k, y = self.net.choose(self.feat, default_candidate(n), self.margin)
+        nv, sh = mlp_candidate(k)
+        return nv, sh, k, y
+
+
+# ---------------------------------------------------------------------------
+# Sweep and training
+# ---------------------------------------------------------------------------
+def make_cloud(seed: int, i: int, n: int) -> np.ndarray:
+    """Cloud i of a sweep: even i room-like, odd i LiDAR-like, n points."""
+    import synth
+    ss = np.random.SeedSequence([seed, i])
+    if i % 2 == 0:
+        return synth.room(ss, n=n)
+    beams = 64 if n < 300_000 else 128
+    steps = int(math.ceil(n / (beams * 0.995)))
+    return synth.lidar(ss, beams=beams, azimuth_steps=steps, n_out=n)
+
+
+def sweep_cloud(x: torch.Tensor, m: int, idx=None):
+    """Build + sample time (ms) and pruning rate of every candidate on one
+    cloud, one timed run each after one warm-up run of the default."""
+    stream = torch.cuda.current_stream(x.device)
+    n = x.shape[0]
+    out_i = torch.empty(m, dtype=torch.int32, device=x.device)
+    out_d = torch.empty(m, dtype=torch.float32, device=x.device)
+    nv0 = default_n_vox(n)
+    idx = build_index(x, n_vox=nv0, reuse=idx)
+    sample(idx, m, 0, out_idx=out_i, out_d2=out_d)
+    torch.cuda.synchronize()
+    ref = out_i.clone()
+    ms = np.zeros(MLP_CANDIDATES)
+    prune = np.zeros(MLP_CANDIDATES)
+    for k, (nv, sh) in enumerate(candidates()):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        idx = build_index(x, n_vox=nv, shell=sh, reuse=idx)
+        sample(idx, m, 0, flags=F_TELEMETRY, out_idx=out_i, out_d2=out_d)
+        b.record(stream)
+        torch.cuda.synchronize()
+        st = read_status(idx)
+        if st != 0:
+            raise RuntimeError("candidate %d failed with status %d" % (k, st))
+        if not torch.equal(out_i, ref):
+            raise RuntimeError("candidate %d changed the sampled sequence" % k)
+        tel = read_telemetry(idx)
+        ms[k] = a.elapsed_time(b)
+        prune[k] = 1.0 - tel["points_visited"] / max(1, tel["iters"] * n)
+    return ms, prune, idx
+
+
+def targets(ms, prune):
+    """Network targets of one cloud: ln(ms_k) minus its mean over the
+    candidates (the ranking is what matters), and the pruning rates."""
+    lm = np.log(ms)
+    return np.concatenate([lm - lm.mean(), prune]).astype(np.float32)
+
+
+def train(X, T, device, steps=4000, lr=1e-3, seed=0, log=None):
+    """Full-batch Adam on the GPU with the library's training kernels."""
+    net = MLP(device, rows=X.shape[0])
+    net.load(init_params(seed))
+    Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(device)
+    Td = torch.from_numpy(np.ascontiguousarray(T, dtype=np.float32)).to(device)
+    # the ranking head counts fully, the pruning-rate head a quarter
+    W = np.ones_like(T)
+    W[:, MLP_CANDIDATES:] = 0.25
+    Wd = torch.from_numpy(W).to(device)
+    loss = torch.empty(1, dtype=torch.float32, device=device)
+    hist = []
+    for s in range(steps):
+        net.train_step(Xd, Td, Wd, lr=lr, loss=loss)
+        if s % 500 == 0 or s == steps - 1:
+            hist.append((s, float(loss.item())))
+            if log:
+                log("  step %d loss %.5f" % hist[-1])
+    return net, hist
+
+
+def evaluate(net, X, MS, N, margin):
+    """Per cloud: time of the default, of the network's choice and of the
+    sweep's best, from the measured sweep."""
+    y = net.forward(torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(net.device)).cpu().numpy()
+    rows = []
+    for b in range(X.shape[0]):
+        d = default_candidate(int(N[b]))
+        pred = y[b, :MLP_CANDIDATES]
+        k = int(np.argmin(pred))
+        if not pred[k] < pred[d] - margin:
+            k = d
+        best = int(np.argmin(MS[b]))
+        rows.append({"n": int(N[b]), "default": d, "choice": k, "best": best, "ms_default": float(MS[b, d]),
+                     "ms_choice": float(MS[b, k]), "ms_best": float(MS[b, best])})
+    gain = float(np.exp(np.mean([math.log(r["ms_default"] / r["ms_choice"]) for r in rows])))
+    regret = float(np.exp(np.mean([math.log(r["ms_choice"] / r["ms_best"]) for r in rows])))
+    headroom = float(np.exp(np.mean([math.log(r["ms_default"] / r["ms_best"]) for r in rows])))
+    return {"gain_vs_default": gain, "regret_vs_best": regret, "best_vs_default": headroom, "clouds": rows}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="sweep, train and evaluate the voxel-parameter network")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--train-clouds", type=int, default=256)
+    ap.add_argument("--heldout-clouds", type=int, default=32)
+    ap.add_argument("--n-min", type=int, default=8000)
+    ap.add_argument("--n-max", type=int, default=1 << 20)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--margin", type=float, default=0.02)
+    ap.add_argument("--seed", type=int, default=2606)
+    ap.add_argument("--sweep", default="", help="reuse a saved sweep (npz) instead of measuring")
+    args = ap.parse_args(argv)
+    os.makedirs(args.out, exist_ok=True)
+
+    def log(*a):
+        print(*a, flush=True)
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    total = args.train_clouds + args.heldout_clouds
+    if args.sweep:
+        d = np.load(args.sweep, allow_pickle=False)
+        X, MS, PR, N = d["X"], d["MS"], d["PR"], d["N"]
+    else:
+        rng = np.random.default_rng(args.seed)
+        sizes = np.floor(np.exp(rng.uniform(math.log(args.n_min), math.log(args.n_max), total))).astype(np.int64)
+        net = MLP(dev)
+        X = np.zeros((total + 1, MLP_INPUTS), dtype=np.float32)
+        MS = np.zeros((total + 1, MLP_CANDIDATES))
+        PR = np.zeros((total + 1, MLP_CANDIDATES))
+        N = np.zeros(total + 1, dtype=np.int64)
+        idx = None
+        t0 = time.time()
+        for i in range(total + 1):
+            if i < total:
+                P, n = make_cloud(args.seed, i, int(sizes[i])), int(sizes[i])
+                m = n // 4
+            else:
+                import synth
+                P = synth.dense_lidar(0)
+                n, m = P.shape[0], 65536
+            x = torch.from_numpy(P).to(dev)
+            X[i] = net.features(x).cpu().numpy()
+            MS[i], PR[i], idx = sweep_cloud(x, m, idx)
+            N[i] = n
+            log("cloud %d/%d N=%d M=%d default %.2f ms best %.2f ms (cand %d) worst %.2f ms  [%.0f s]" % (
+                i + 1, total + 1, n, m, MS[i, default_candidate(n)], MS[i].min(), int(np.argmin(MS[i])),
+                MS[i].max(), time.time() - t0))
+            if i % 16 == 15 or i == total:
+                np.savez(os.path.join(args.out, "sweep.npz"), X=X[:i + 1], MS=MS[:i + 1], PR=PR[:i + 1],
+                         N=N[:i + 1])
+    ntr = args.train_clouds
+    T = np.stack([targets(MS[i], PR[i]) for i in range(X.shape[0])])
+    log("training on %d clouds" % ntr)
+    net, hist = train(X[:ntr], T[:ntr], dev, steps=args.steps, lr=args.lr, seed=args.seed, log=log)
+    params = net.save()
+    report = {"train": evaluate(net, X[:ntr], MS[:ntr], N[:ntr], args.margin),
+              "heldout": evaluate(net, X[ntr:-1], MS[ntr:-1], N[ntr:-1], args.margin),
+              "dense_lidar_1M": evaluate(net, X[-1:], MS[-1:], N[-1:], args.margin),
+              "loss": hist, "margin": args.margin, "train_clouds": ntr, "heldout_clouds": int(X.shape[0] - ntr - 1),
+              "steps": args.steps, "lr": args.lr, "seed": args.seed}
+    for k in ("train", "heldout", "dense_lidar_1M"):
+        r = report[k]
+        log("%s: gain vs default %.3fx, regret vs best %.3fx, best vs default %.3fx" % (
+            k, r["gain_vs_default"], r["regret_vs_best"], r["best_vs_default"]))
+    np.savez(os.path.join(args.out, "param_mlp.npz"), params=params, margin=np.float32(args.margin))
+    with open(os.path.join(args.out, "param_report.json"), "w") as f:
+        json.dump(report, f, indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -174,8 +174,8 @@ def test_shell_parameter(L):
 
 def test_mlp_host_checks(L):
     import paper_2606_06255_amd as rf
-    assert rf.mlp_candidate(0) == (8, 0.0) and rf.mlp_candidate(35) == (128, 20.0)
-    assert rf.mlp_candidate(13) == (24, 5.0)
+    assert rf.mlp_candidate(0) == (12, 0.0) and rf.mlp_candidate(35) == (192, 20.0)
+    assert rf.mlp_candidate(13) == (32, 5.0)
     with pytest.raises(ValueError):
         rf.mlp_candidate(36)
     assert L.rfps_mlp_state_size() >= 4 * 3 * rf.MLP_PARAMS

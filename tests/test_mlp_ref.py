@@ -145,5 +145,5 @@ def test_adam_first_step_closed_form():
 
 def test_candidates():
     assert R.N_CAND == 36 and R.OUT == 72 and R.N_PARAMS == 41928
-    assert R.candidate(0) == (8, 0.0) and R.candidate(35) == (128, 20.0)
+    assert R.candidate(0) == (12, 0.0) and R.candidate(35) == (192, 20.0)
     assert len({R.candidate(k) for k in range(R.N_CAND)}) == 36
