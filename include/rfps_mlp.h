@@ -25,7 +25,7 @@
  *
  * Features of a cloud of N points (float32): f[0] = (ln N - 11) / 2;
  * f[1..3] = ln(1 + E_a) / 2 with E_a the bounding-box extents; f[4 + c] =
- * 64 * count_c / N for the cells c = (z * 8 + y) * 8 + x of a cubic 8^3
+ * ln(1 + 64 * count_c / N) for the cells c = (z * 8 + y) * 8 + x of a cubic 8^3
  * grid of edge (1 + 1e-4) * max(E) / 8 from the box minimum (FP64
  * coordinates, clamped to the grid).
  *

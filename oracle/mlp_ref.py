@@ -56,9 +56,9 @@ def bf16_round(x):
 
 def features(xyz):
     """516 features of a cloud: (ln N - 11) / 2, ln(1 + E_a) / 2 for the
-    three bounding-box extents, and 64 * count / N for the 8^3 cells of a
-    cubic grid over the box (cell edge (1 + 1e-4) * max(E) / 8, FP64
-    coordinates, clamped).  Returned as float32."""
+    three bounding-box extents, and ln(1 + 64 * count / N) for the 8^3 cells
+    of a cubic grid over the box (cell edge (1 + 1e-4) * max(E) / 8, FP64
+    coordinates, clamped).  Returned as float32, with the integer counts."""
     p = np.asarray(xyz, dtype=np.float32).astype(np.float64)
     n = p.shape[0]
     lo, hi = p.min(axis=0), p.max(axis=0)
@@ -72,7 +72,7 @@ def features(xyz):
     f = np.empty(F_IN, dtype=np.float64)
     f[0] = (np.log(float(n)) - 11.0) / 2.0
     f[1:4] = np.log1p(E) / 2.0
-    f[4:] = 64.0 * counts / n
+    f[4:] = np.log1p(64.0 * counts / n)
     return f.astype(np.float32), counts.astype(np.int64)
 
 

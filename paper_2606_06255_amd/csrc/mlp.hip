@@ -202,7 +202,9 @@ __global__ __launch_bounds__(256) void k_load(float *__restrict__ w, float *__re
 // ---------------------------------------------------------------------------
 // Features: bounding box, 8^3 occupancy histogram over a cubic grid of edge
 // (1 + 1e-4) max(E) / 8 from the box minimum (FP64, clamped), then
-// f0 = (ln N - 11) / 2, f1..3 = ln(1 + E_a) / 2, f(4 + cell) = 64 count / N.
+// f0 = (ln N - 11) / 2, f1..3 = ln(1 + E_a) / 2, f(4 + cell) =
+// ln(1 + 64 count / N) (the logarithm tames the dense near-sensor cells of
+// a spinning scan).
 // ---------------------------------------------------------------------------
 struct FeatScratch {
     uint32_t status;
@@ -305,7 +307,7 @@ __global__ void k_feat_final(int n, const FeatScratch *__restrict__ fs, float *_
             const int a = t - 1;
             v = log1p((double)ord2f(fs->bb[3 + a]) - (double)ord2f(fs->bb[a])) / 2.0;
         } else {
-            v = 64.0 * (double)fs->counts[t - 4] / (double)n;
+            v = log1p(64.0 * (double)fs->counts[t - 4] / (double)n);
         }
         f[t] = fs->status ? __uint_as_float(0x7fc00000u) : (float)v;
     }

@@ -24,7 +24,9 @@
 //      the group with the largest bound still has its true key equal to its
 //      local key (no other pick of the round lowered it), that candidate is
 //      exactly the next FPS selection (the Sec. 3.1 rule; keys are unique).
-//      Otherwise the round ends;
+//      Otherwise the round ends.  This visits the candidates in descending
+//      order of local key, so the merge sorts them and certifies them in that
+//      order, all threads of the workgroup at once;
 //   A  apply: all picks of the round update the true state (spherical test
 //      per tile and pick, point skip, strict update, tile-key resync).
 //
@@ -61,14 +63,22 @@ struct RoundArgs {
 };
 
 // Selections one round may settle (the merge stops there; a shorter round is
-// always valid).  The merge keeps the round's picks in registers, eight per
-// lane of its wavefront.
-constexpr int kRoundPickSlots = 8;
-constexpr int kMaxRoundPicks = kWave * kRoundPickSlots;
+// always valid).
+constexpr int kMaxRoundPicks = 512;
+
+// Entries of the merge's sort buffer: the next power of two of G * R (at least 64).
+__host__ __device__ __forceinline__ uint32_t sort_cap(uint32_t G, uint32_t R)
+{
+    uint32_t s = kWave;
+    while (s < G * R)
+        s <<= 1;
+    return s;
+}
 
 __host__ __device__ __forceinline__ uint32_t rounds_lds_need(uint32_t tiles, uint32_t pts, uint32_t G, uint32_t R)
 {
-    return tiles * 60u + pts * 24u + G * R * 24u + G * (R + 1u) * 8u + kMaxRoundPicks * 16u + 128u;
+    return tiles * 60u + pts * 24u + G * R * 24u + G * (R + 1u) * 8u + sort_cap(G, R) * 4u + kMaxRoundPicks * 12u +
+           128u;
 }
 
 // Capacity plan of one team of G workgroups over the tiles [tb, te).
@@ -144,7 +154,8 @@ struct RoundShared {
     unsigned long long red[kWavesPerBlock];
     uint32_t redi[kWavesPerBlock];
     uint32_t scan[kWavesPerBlock];
-    uint32_t abort, list_n, npick;
+    uint32_t abort, list_n, npick, mcount, mfail;
+    uint32_t cmin[kWave];  // merge: true distances of one chunk of 64 positions (float bits)
     uint32_t my[6 * 8 + 2];  // this workgroup's slot payload (R <= 8)
 };
 
@@ -202,8 +213,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
     float *ctd = cz + G * R;   // true round-start d2; becomes the selection d2 when picked
     float *cld = ctd + G * R;  // local d2
     uint32_t *corig = reinterpret_cast<uint32_t *>(cld + G * R);
-    uint32_t *picks = corig + G * R;  // candidate index g*R+h of each pick of the round
-    float *pkx = reinterpret_cast<float *>(picks + kMaxRoundPicks);  // pick coordinates, in order
+    uint32_t *sidx = corig + G * R;  // merge order; its first P entries are the round's picks
+    float *pkx = reinterpret_cast<float *>(sidx + sort_cap(G, R));  // pick coordinates, in order
     float *pky = pkx + kMaxRoundPicks;
     float *pkz = pky + kMaxRoundPicks;
     float *px = pkz + kMaxRoundPicks;
@@ -394,44 +405,93 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             if (lane == 0)
                 bstore<S>(slot + W - 1, ((unsigned long long)epoch << 32) | sh.my[W - 1]);
         }
+        // wait until the last word of every slot carries the epoch (one word
+        // polled per slot), then read all words of all slots word-major, so
+        // that neighbouring threads read neighbouring words; a word counts
+        // once it carries the epoch (each word is checked: words of one slot
+        // need not become visible in the order they were written)
         if (tid < G) {
-            const unsigned long long *slot = board + ((size_t)(epoch & 1u) * G + tid) * kMaxSlotWords;
-            bool ok = false;
-            for (uint32_t spin = 0; spin < kSpinLimit && !ok; ++spin) {
+            const unsigned long long *last = board + ((size_t)(epoch & 1u) * G + tid) * kMaxSlotWords + W - 1;
+            uint32_t spin = 0;
+            for (; spin < kSpinLimit; ++spin) {
                 binvalidate<S>();
-                const unsigned long long r = bload<S>(slot + W - 1);
-                if ((uint32_t)(r >> 32) == kAbortEpoch)
+                const uint32_t ep = (uint32_t)(bload<S>(last) >> 32);
+                if (ep == epoch)
                     break;
-                if ((uint32_t)(r >> 32) != epoch)
-                    continue;
-                uint32_t v[W];
-                ok = true;
+                if (ep == kAbortEpoch)
+                    spin = kSpinLimit - 1;
+            }
+            if (spin >= kSpinLimit)
+                sh.abort = 1;
+        }
+        __syncthreads();
+        if (!sh.abort) {
+            const int total = G * W;
+            const unsigned long long *sbase = board + (size_t)(epoch & 1u) * G * kMaxSlotWords;
+            unsigned long long pend = 0;
 #pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    const unsigned long long x = bload<S>(slot + w);
-                    ok &= (uint32_t)(x >> 32) == epoch;
-                    v[w] = (uint32_t)x;
+            for (int r = 0; r < W; ++r)
+                pend |= (tid + kBlock * r < total) ? (1ull << r) : 0ull;
+            bool ab = false;
+            constexpr int kChunk = 8;  // loads in flight per thread
+            for (uint32_t spin = 0; pend && !ab && spin < kSpinLimit; ++spin) {
+                binvalidate<S>();
+#pragma unroll 1
+                for (int r0 = 0; r0 < W; r0 += kChunk) {
+                unsigned long long x[kChunk];
+#pragma unroll
+                for (int q = 0; q < kChunk; ++q) {
+                    const int r = r0 + q, e = tid + kBlock * r;
+                    x[q] = (r < W && ((pend >> r) & 1ull))
+                               ? bload<S>(sbase + (size_t)(e / W) * kMaxSlotWords + e % W)
+                               : 0ull;
                 }
-                if (ok) {
-                    // a workgroup without tiles publishes the bound key 0 and no candidates
-                    const bool empty = v[6 * R] == 0u && v[6 * R + 1] == 0u;
 #pragma unroll
-                    for (int s = 0; s < R; ++s) {
-                        const int c = tid * R + s;
-                        cx[c] = __uint_as_float(v[6 * s + 0]);
-                        cy[c] = __uint_as_float(v[6 * s + 1]);
-                        cz[c] = __uint_as_float(v[6 * s + 2]);
-                        ctd[c] = __uint_as_float(v[6 * s + 3]);
-                        corig[c] = v[6 * s + 4];
-                        cld[c] = __uint_as_float(v[6 * s + 5]);
-                        bkey[tid * (R + 1) + s] =
-                            empty ? 0ull : ((unsigned long long)v[6 * s + 5] << 32) | (~v[6 * s + 4]);
+                for (int q = 0; q < kChunk; ++q) {
+                    const int r = r0 + q;
+                    if (r >= W || !((pend >> r) & 1ull))
+                        continue;
+                    const unsigned long long xr = x[q];
+                    const uint32_t ep = (uint32_t)(xr >> 32);
+                    ab |= ep == kAbortEpoch;
+                    if (ep != epoch)
+                        continue;
+                    pend &= ~(1ull << r);
+                    const int e = tid + kBlock * r, g = e / W, w = e % W;
+                    const uint32_t v = (uint32_t)xr;
+                    if (w < 6 * R) {
+                        const int c = g * R + w / 6;
+                        switch (w % 6) {
+                        case 0: cx[c] = __uint_as_float(v); break;
+                        case 1: cy[c] = __uint_as_float(v); break;
+                        case 2: cz[c] = __uint_as_float(v); break;
+                        case 3: ctd[c] = __uint_as_float(v); break;
+                        case 4: corig[c] = v; break;
+                        default: cld[c] = __uint_as_float(v); break;
+                        }
+                    } else {
+                        // the bound key: high half first (little-endian halves)
+                        reinterpret_cast<uint32_t *>(bkey + g * (R + 1) + R)[w == 6 * R ? 1 : 0] = v;
                     }
-                    bkey[tid * (R + 1) + R] = ((unsigned long long)v[6 * R] << 32) | v[6 * R + 1];
+                }
                 }
             }
-            if (!ok)
+            if (pend)
                 sh.abort = 1;
+        }
+        __syncthreads();
+        if (!sh.abort) {
+            // candidate keys; a workgroup without tiles publishes the bound 0
+            // and no candidates
+            for (int g = tid; g < G; g += kBlock) {
+                const bool empty = bkey[g * (R + 1) + R] == 0ull;
+#pragma unroll
+                for (int s2 = 0; s2 < R; ++s2) {
+                    const int c = g * R + s2;
+                    bkey[g * (R + 1) + s2] =
+                        empty ? 0ull : ((unsigned long long)__float_as_uint(cld[c]) << 32) | (~corig[c]);
+                }
+            }
         }
         __syncthreads();
         if (sh.abort) {
@@ -450,105 +510,104 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             t_mark = t;
         }
 
-        // =============== M: certified merge (wavefront 0) ===============
-        // Lane l tracks groups l, l+64, l+128, l+192: head index and bound key
-        // (the local key of the head candidate, or k_{R+1} once exhausted).
-        // The round's picks live in registers, pick k in lane k % 64, slot k / 64.
-        if (wave == 0) {
-            int hq[4];
-            unsigned long long hk[4];
+        // =============== M: certified merge (whole workgroup) ===============
+        // Candidates are taken in descending order of local key; each one is
+        // certified when its true distance (the round-start value lowered by
+        // every earlier pick of the round) still equals its local distance,
+        // and the round ends at the first one that is not.  Taking the group
+        // with the largest bound B_g at every step visits exactly this order
+        // until the largest published bound S* = max_g k_{R+1} is reached,
+        // where it stops as well; so the candidates above S* are compacted,
+        // sorted (bitonic, in LDS) and certified 64 positions at a time.
+        {
+            unsigned long long sk = 0;
+            for (int g = tid; g < G; g += kBlock)
+                sk = umax64(sk, bkey[g * (R + 1) + R]);
+            sk = wave_max_u64(sk);
+            if (lane == 0)
+                sh.red[wave] = sk;
+            if (tid == 0)
+                sh.mcount = 0;
+            __syncthreads();
+            unsigned long long smax = 0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int gg = lane + kWave * q;
-                hk[q] = gg < G ? bkey[gg * (R + 1)] : 0ull;
-                hq[q] = hk[q] != 0ull ? 0 : R;  // empty group: never the maximum
+            for (int q = 0; q < kWavesPerBlock; ++q)
+                smax = umax64(smax, sh.red[q]);
+            for (int c = tid; c < G * R; c += kBlock) {
+                if (bkey[(c / R) * (R + 1) + c % R] > smax)
+                    sidx[atomicAdd(&sh.mcount, 1u)] = (uint32_t)c;
             }
-            float qx[kRoundPickSlots], qy[kRoundPickSlots], qz[kRoundPickSlots];
-#pragma unroll
-            for (int s = 0; s < kRoundPickSlots; ++s)
-                qx[s] = qy[s] = qz[s] = 0.0f;
-            const int pmax = min(job.m - j, kMaxRoundPicks);
-            int P = 0;
-            while (P < pmax) {
-                // group with the largest bound (keys are unique)
-                unsigned long long lb = 0;
-                int lq = 0;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (hk[q] > lb) {
-                        lb = hk[q];
-                        lq = q;
-                    }
-                }
-                const uint32_t mhi = wave_max_u32((uint32_t)(lb >> 32));
-                unsigned long long hit = __ballot((uint32_t)(lb >> 32) == mhi && lb != 0ull);
-                if (!hit)
-                    break;
-                if (__popcll(hit) > 1) {  // equal distances: the larger low half (smaller index) wins
-                    const uint32_t mlo = wave_max_u32((uint32_t)(lb >> 32) == mhi ? (uint32_t)lb : 0u);
-                    hit = __ballot((uint32_t)(lb >> 32) == mhi && (uint32_t)lb == mlo && lb != 0ull);
-                }
-                const int L0 = __ffsll((long long)hit) - 1;
-                const int bq = __builtin_amdgcn_readlane(lq, L0);
-                int mh = R;
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    mh = q == bq ? hq[q] : mh;
-                const int oh = __builtin_amdgcn_readlane(mh, L0);
-                if (oh >= R)
-                    break;  // that group's next candidate is beyond its lookahead
-                const int gs = L0 + kWave * bq;
-                const int cidx = gs * R + oh;
-                const float ox = cx[cidx], oy = cy[cidx], oz = cz[cidx];
-                const float ol = cld[cidx];
-                // true distance of the head now: round-start value lowered by every pick so far
-                float t = ctd[cidx];
-#pragma unroll
-                for (int s = 0; s < kRoundPickSlots; ++s) {
-                    if (s * kWave < P && s * kWave + lane < P)
-                        t = fminf(t, sqdist(ox, oy, oz, qx[s], qy[s], qz[s]));
-                }
-                t = wave_min_dist(t);
-                if (!(t == ol))
-                    break;  // a pick of this round lowered it: the bound is not attained
-                // certified: record the selection
-                const int ps = P / kWave, pl = P % kWave;
-#pragma unroll
-                for (int s = 0; s < kRoundPickSlots; ++s) {
-                    if (s == ps && lane == pl) {
-                        qx[s] = ox;
-                        qy[s] = oy;
-                        qz[s] = oz;
-                    }
-                }
-                if (lane == 0) {
-                    picks[P] = (uint32_t)cidx;
-                    pkx[P] = ox;
-                    pky[P] = oy;
-                    pkz[P] = oz;
-                    ctd[cidx] = t;  // distance at selection
-                }
-                ++P;
-                // advance the owner's head
-                if (lane == L0) {
-                    const unsigned long long nk = bkey[gs * (R + 1) + oh + 1];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        if (q == bq) {
-                            hq[q] = oh + 1;
-                            hk[q] = nk;
+            __syncthreads();
+            const uint32_t L = sh.mcount;
+            uint32_t sn = kWave;
+            while (sn < L)
+                sn <<= 1;
+            for (uint32_t e = L + tid; e < sn; e += kBlock)
+                sidx[e] = 0xffffffffu;  // key 0: sorts last
+            __syncthreads();
+            for (uint32_t k = 2; k <= sn; k <<= 1) {
+                for (uint32_t h = k >> 1; h > 0; h >>= 1) {
+                    for (uint32_t q = tid; q < sn / 2; q += kBlock) {
+                        const uint32_t e = ((q & ~(h - 1)) << 1) | (q & (h - 1));
+                        const uint32_t f = e + h;
+                        const uint32_t ca = sidx[e], cb = sidx[f];
+                        const unsigned long long ka = ca == 0xffffffffu ? 0ull : bkey[(ca / R) * (R + 1) + ca % R];
+                        const unsigned long long kb = cb == 0xffffffffu ? 0ull : bkey[(cb / R) * (R + 1) + cb % R];
+                        if ((e & k) == 0 ? ka < kb : ka > kb) {
+                            sidx[e] = cb;
+                            sidx[f] = ca;
                         }
                     }
+                    __syncthreads();
                 }
             }
-            if (lane == 0)
-                sh.npick = (uint32_t)P;
+            const uint32_t pmax = min(min(L, (uint32_t)kMaxRoundPicks), (uint32_t)(job.m - j));
+            uint32_t P = 0;
+            for (uint32_t base = 0; base < pmax; base += kWave) {
+                const uint32_t n = min((uint32_t)kWave, pmax - base);
+                if (tid < (int)n)
+                    sh.cmin[tid] = __float_as_uint(ctd[sidx[base + tid]]);
+                __syncthreads();
+                if ((uint32_t)lane < n) {
+                    // distances to every earlier position, split over the waves
+                    const uint32_t e = base + lane, c = sidx[e];
+                    const float x = cx[c], y = cy[c], z = cz[c];
+                    float t = INFINITY;
+                    for (uint32_t q = wave; q < e; q += kWavesPerBlock) {
+                        const uint32_t cq = sidx[q];
+                        t = fminf(t, sqdist(x, y, z, cx[cq], cy[cq], cz[cq]));
+                    }
+                    atomicMin(&sh.cmin[lane], __float_as_uint(t));
+                }
+                __syncthreads();
+                if (wave == 0) {
+                    const bool fail = (uint32_t)lane < n && __uint_as_float(sh.cmin[lane]) != cld[sidx[base + lane]];
+                    const unsigned long long fm = __ballot(fail);
+                    if (lane == 0)
+                        sh.mfail = fm ? (uint32_t)(__ffsll((long long)fm) - 1) : n;
+                }
+                __syncthreads();
+                const uint32_t ok = sh.mfail;
+                if (tid < (int)ok) {
+                    const uint32_t c = sidx[base + tid];
+                    pkx[base + tid] = cx[c];
+                    pky[base + tid] = cy[c];
+                    pkz[base + tid] = cz[c];
+                    ctd[c] = __uint_as_float(sh.cmin[tid]);  // the distance at selection
+                }
+                P = base + ok;
+                __syncthreads();
+                if (ok < n)
+                    break;
+            }
+            if (tid == 0)
+                sh.npick = P;
             if (rank == 0) {
-                for (int k = lane; k < P; k += kWave) {
-                    const uint32_t pc = picks[k];
-                    job.out_idx[j + k] = (int32_t)corig[pc];
+                for (uint32_t k = tid; k < P; k += kBlock) {
+                    const uint32_t c = sidx[k];
+                    job.out_idx[j + k] = (int32_t)corig[c];
                     if (job.out_d2)
-                        job.out_d2[j + k] = ctd[pc];
+                        job.out_d2[j + k] = ctd[c];
                 }
             }
         }

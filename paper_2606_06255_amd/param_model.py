@@ -78,12 +78,31 @@ class ParamModel:
         self.feat = torch.empty(MLP_INPUTS, dtype=torch.float32, device=device)
 
     def choose(self, xyz: torch.Tensor):
-        """(n_vox, shell spacing, candidate, predictions): waits for the device."""
+        """(n_vox, shell spacing, candidate, predictions): waits for the device.
+        A grid whose share per workgroup exceeds the on-chip budget makes
+        the sampler report RFPS_ERR_CAPACITY; callers then index with the
+        default rule (see fps_auto)."""
         n = xyz.shape[0]
         self.net.features(xyz, out=self.feat)
         k, y = self.net.choose(self.feat, default_candidate(n), self.margin)
         nv, sh = mlp_candidate(k)
         return nv, sh, k, y
+
+
+def fps_auto(model: ParamModel, xyz: torch.Tensor, m: int, start: int = 0, **kw):
+    """Exact FPS with the network's grid, falling back to the default rule
+    when the chosen grid does not fit on chip.  Returns (idx, d2, (n_vox, shell))."""
+    from . import RfpsError, fps
+    nv, sh, _, _ = model.choose(xyz)
+    try:
+        i, d = fps(xyz, m, start, n_vox=nv, shell=sh, **kw)
+        return i, d, (nv, sh)
+    except RfpsError as e:
+        if e.status != 6:
+            raise
+    nv0 = default_n_vox(xyz.shape[0])
+    i, d = fps(xyz, m, start, n_vox=nv0, **kw)
+    return i, d, (nv0, 0.0)
 
 
 # ---------------------------------------------------------------------------
@@ -122,6 +141,10 @@ def sweep_cloud(x: torch.Tensor, m: int, idx=None):
         b.record(stream)
         torch.cuda.synchronize()
         st = read_status(idx)
+        if st == 6:
+            # this grid's share per workgroup does not fit on chip: not a choice
+            ms[k], prune[k] = np.nan, np.nan
+            continue
         if st != 0:
             raise RuntimeError("candidate %d failed with status %d" % (k, st))
         if not torch.equal(out_i, ref):
@@ -134,9 +157,13 @@ def sweep_cloud(x: torch.Tensor, m: int, idx=None):
 
 def targets(ms, prune):
     """Network targets of one cloud: ln(ms_k) minus its mean over the
-    candidates (the ranking is what matters), and the pruning rates."""
-    lm = np.log(ms)
-    return np.concatenate([lm - lm.mean(), prune]).astype(np.float32)
+    candidates (the ranking is what matters), and the pruning rates.  A
+    candidate that does not fit on chip gets the slowest time plus ln 2."""
+    ok = np.isfinite(ms)
+    lm = np.log(np.where(ok, ms, 1.0))
+    lm[~ok] = lm[ok].max() + math.log(2.0)
+    pr = np.where(ok, prune, 0.0)
+    return np.concatenate([lm - lm.mean(), pr]).astype(np.float32)
 
 
 def train(X, T, device, steps=4000, lr=1e-3, seed=0, log=None):
@@ -169,9 +196,9 @@ def evaluate(net, X, MS, N, margin):
         d = default_candidate(int(N[b]))
         pred = y[b, :MLP_CANDIDATES]
         k = int(np.argmin(pred))
-        if not pred[k] < pred[d] - margin:
-            k = d
-        best = int(np.argmin(MS[b]))
+        if not pred[k] < pred[d] - margin or not np.isfinite(MS[b, k]):
+            k = d  # no clear predicted win, or a grid that does not fit: the default
+        best = int(np.nanargmin(MS[b]))
         rows.append({"n": int(N[b]), "default": d, "choice": k, "best": best, "ms_default": float(MS[b, d]),
                      "ms_choice": float(MS[b, k]), "ms_best": float(MS[b, best])})
     gain = float(np.exp(np.mean([math.log(r["ms_default"] / r["ms_choice"]) for r in rows])))
@@ -187,9 +214,9 @@ def main(argv=None):
     ap.add_argument("--heldout-clouds", type=int, default=32)
     ap.add_argument("--n-min", type=int, default=8000)
     ap.add_argument("--n-max", type=int, default=1 << 20)
-    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--margin", type=float, default=0.02)
+    ap.add_argument("--margin", type=float, default=0.03)
     ap.add_argument("--seed", type=int, default=2606)
     ap.add_argument("--sweep", default="", help="reuse a saved sweep (npz) instead of measuring")
     args = ap.parse_args(argv)
@@ -202,8 +229,22 @@ def main(argv=None):
     torch.cuda.set_device(dev)
     total = args.train_clouds + args.heldout_clouds
     if args.sweep:
+        # reuse measured times; the features are recomputed on the GPU from
+        # the regenerated clouds (same seeds and sizes)
         d = np.load(args.sweep, allow_pickle=False)
-        X, MS, PR, N = d["X"], d["MS"], d["PR"], d["N"]
+        MS, PR, N = d["MS"], d["PR"], d["N"]
+        X = np.zeros((N.size, MLP_INPUTS), dtype=np.float32)
+        net = MLP(dev)
+        for i in range(N.size):
+            if i < N.size - 1:
+                P = make_cloud(args.seed, i, int(N[i]))
+            else:
+                import synth
+                P = synth.dense_lidar(0)
+            X[i] = net.features(torch.from_numpy(P).to(dev)).cpu().numpy()
+            if i % 32 == 31:
+                log("features %d/%d" % (i + 1, N.size))
+        np.savez(os.path.join(args.out, "sweep.npz"), X=X, MS=MS, PR=PR, N=N)
     else:
         rng = np.random.default_rng(args.seed)
         sizes = np.floor(np.exp(rng.uniform(math.log(args.n_min), math.log(args.n_max), total))).astype(np.int64)
@@ -226,9 +267,9 @@ def main(argv=None):
             X[i] = net.features(x).cpu().numpy()
             MS[i], PR[i], idx = sweep_cloud(x, m, idx)
             N[i] = n
-            log("cloud %d/%d N=%d M=%d default %.2f ms best %.2f ms (cand %d) worst %.2f ms  [%.0f s]" % (
-                i + 1, total + 1, n, m, MS[i, default_candidate(n)], MS[i].min(), int(np.argmin(MS[i])),
-                MS[i].max(), time.time() - t0))
+            log("cloud %d/%d N=%d M=%d default %.2f ms best %.2f ms (cand %d) worst %.2f ms, %d unfit  [%.0f s]" % (
+                i + 1, total + 1, n, m, MS[i, default_candidate(n)], np.nanmin(MS[i]), int(np.nanargmin(MS[i])),
+                np.nanmax(MS[i]), int(np.isnan(MS[i]).sum()), time.time() - t0))
             if i % 16 == 15 or i == total:
                 np.savez(os.path.join(args.out, "sweep.npz"), X=X[:i + 1], MS=MS[:i + 1], PR=PR[:i + 1],
                          N=N[:i + 1])

@@ -49,10 +49,11 @@ def test_features(rf, dev, cloud):
     net = rf.MLP(dev)
     f = net.features(torch.from_numpy(pts).to(dev)).cpu().numpy()
     ref, counts = R.features(pts)
-    # the occupancy features are decided by FP64 bin comparisons on both sides: exact
-    assert np.array_equal(f[4:], ref[4:])
-    assert np.allclose(f[:4], ref[:4], rtol=1e-6, atol=1e-7)
-    assert np.isclose(f[4:].sum(), 64.0, rtol=1e-5)
+    # the cell counts are decided by FP64 bin comparisons on both sides: exact
+    n = pts.shape[0]
+    got_counts = np.rint(np.expm1(f[4:].astype(np.float64)) * n / 64.0).astype(np.int64)
+    assert np.array_equal(got_counts, counts)
+    assert np.allclose(f, ref, rtol=1e-6, atol=1e-7)
 
 
 def test_features_nonfinite(rf, dev):

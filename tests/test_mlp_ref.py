@@ -54,7 +54,8 @@ def test_features_brute_force():
     assert counts[0] == 1 and counts[511] == 1 and counts[(3 * 8 + 3) * 8 + 3] == 1
     assert f[0] == np.float32((np.log(9.0) - 11.0) / 2.0)
     assert np.allclose(f[1:4], np.log1p(8.0) / 2.0)
-    assert np.isclose(f[4:].sum(), 64.0)
+    assert np.isclose(np.expm1(f[4:].astype(np.float64)).sum(), 64.0)
+    assert f[4] == np.float32(np.log1p(64.0 / 9.0))
 
 
 def test_features_uniform_cube():
@@ -63,7 +64,7 @@ def test_features_uniform_cube():
     f, counts = R.features(pts)
     assert counts.sum() == pts.shape[0]
     assert counts.min() > 300 and counts.max() < 500
-    assert abs(f[4:].mean() - 0.125) < 1e-6
+    assert abs(np.expm1(f[4:].astype(np.float64)).mean() - 0.125) < 1e-6
 
 
 def test_features_degenerate_cloud():
