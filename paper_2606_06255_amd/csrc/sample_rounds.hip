@@ -533,8 +533,16 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
 #pragma unroll
             for (int q = 0; q < kWavesPerBlock; ++q)
                 smax = umax64(smax, sh.red[q]);
+            // Keys of different points differ, so only a group's own repeats
+            // can tie: once every point of a group has local distance 0, its
+            // lookahead returns its lowest index again and again, and its
+            // bound equals those candidates.  A group's candidates precede its
+            // own bound, so a candidate equal to S* is taken when S* is the
+            // bound of its own group.
             for (int c = tid; c < G * R; c += kBlock) {
-                if (bkey[(c / R) * (R + 1) + c % R] > smax)
+                const int g = c / R;
+                const unsigned long long k = bkey[g * (R + 1) + c % R];
+                if (k > smax || (k == smax && bkey[g * (R + 1) + R] == smax))
                     sidx[atomicAdd(&sh.mcount, 1u)] = (uint32_t)c;
             }
             __syncthreads();
