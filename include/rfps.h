@@ -114,7 +114,10 @@ typedef struct rfps_telemetry {
     int64_t ticks_merge;
     int64_t ticks_apply;
     int64_t tick_hz;        /* rate of those ticks (filled in by the reader) */
-    int64_t reserved[2];
+    /* of ticks_exchange, the part spent waiting until every workgroup had
+     * published (the rest is reading the slots) */
+    int64_t ticks_wait;
+    int64_t reserved;
 } rfps_telemetry;
 
 /* Shape of a built index, read back by rfps_read_index_info(). */

@@ -44,7 +44,7 @@ class rfps_telemetry(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "iters", "tiles", "tile_tests", "tiles_pruned", "points_visited", "points_skipped",
         "points_updated", "tiles_resynced", "exchanges", "ticks_lookahead", "ticks_exchange",
-        "ticks_merge", "ticks_apply", "tick_hz", "reserved0", "reserved1")]
+        "ticks_merge", "ticks_apply", "tick_hz", "ticks_wait", "reserved")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_ if not k.startswith("reserved")}

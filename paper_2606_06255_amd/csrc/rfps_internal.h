@@ -40,6 +40,7 @@ constexpr int kTeleTicksExchange = 10;
 constexpr int kTeleTicksMerge = 11;
 constexpr int kTeleTicksApply = 12;
 constexpr int kTeleTickHz = 13;
+constexpr int kTeleTicksWait = 14;
 
 // Status words live in the index header.  The build status is sticky for the
 // index; the sample status is cleared at the start of every sampling call.

@@ -38,6 +38,8 @@
 // agent-scope atomics (coherent across XCDs); a team whose workgroups all
 // sit on one XCD exchanges through that XCD's L2 (plain stores, L1
 // invalidate before every poll), which halves the exchange latency.
+#include <type_traits>
+
 #include "rfps_internal.h"
 
 namespace rfps {
@@ -66,18 +68,27 @@ struct RoundArgs {
 // always valid).
 constexpr int kMaxRoundPicks = 512;
 
-// Entries of the merge's sort buffer: the next power of two of G * R (at least 64).
+// Entries of the merge's sort buffers: the next power of two of G * R, at
+// least 128 (the smallest network the merge runs).
 __host__ __device__ __forceinline__ uint32_t sort_cap(uint32_t G, uint32_t R)
 {
-    uint32_t s = kWave;
+    uint32_t s = 2 * kWave;
     while (s < G * R)
         s <<= 1;
     return s;
 }
 
+// 4-byte words of the region the merge uses first for its sorted keys and
+// then for the pick coordinates.
+__host__ __device__ __forceinline__ uint32_t merge_words(uint32_t G, uint32_t R)
+{
+    const uint32_t keys = 2u * sort_cap(G, R), picks = 3u * kMaxRoundPicks;
+    return keys > picks ? keys : picks;
+}
+
 __host__ __device__ __forceinline__ uint32_t rounds_lds_need(uint32_t tiles, uint32_t pts, uint32_t G, uint32_t R)
 {
-    return tiles * 60u + pts * 24u + G * R * 24u + G * (R + 1u) * 8u + sort_cap(G, R) * 4u + kMaxRoundPicks * 12u +
+    return tiles * 60u + pts * 24u + G * R * 24u + G * (R + 1u) * 8u + sort_cap(G, R) * 4u + merge_words(G, R) * 4u +
            128u;
 }
 
@@ -162,7 +173,7 @@ struct RoundShared {
 // Per-thread telemetry accumulators.
 struct RoundTele {
     unsigned long long tests = 0, pruned = 0, visited = 0, skipped = 0, updated = 0, resync = 0;
-    unsigned long long ph[4] = {0, 0, 0, 0};
+    unsigned long long ph[5] = {0, 0, 0, 0, 0};  // lookahead, exchange, merge, apply, exchange wait
     unsigned long long rounds = 0;
 };
 
@@ -196,7 +207,12 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
     unsigned long long *tkey = reinterpret_cast<unsigned long long *>(smem);
     unsigned long long *tkeyl = tkey + ntl;
     unsigned long long *bkey = tkeyl + ntl;  // [G][R+1] published local keys
-    float *tcx = reinterpret_cast<float *>(bkey + (size_t)G * (R + 1));
+    // merge: the keys in sort order, then (same memory) the pick coordinates
+    unsigned long long *skey = bkey + (size_t)G * (R + 1);
+    float *pkx = reinterpret_cast<float *>(skey);
+    float *pky = pkx + kMaxRoundPicks;
+    float *pkz = pky + kMaxRoundPicks;
+    float *tcx = reinterpret_cast<float *>(skey) + merge_words(G, R);
     float *tcy = tcx + ntl;
     float *tcz = tcy + ntl;
     float *trad = tcz + ntl;
@@ -214,10 +230,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
     float *cld = ctd + G * R;  // local d2
     uint32_t *corig = reinterpret_cast<uint32_t *>(cld + G * R);
     uint32_t *sidx = corig + G * R;  // merge order; its first P entries are the round's picks
-    float *pkx = reinterpret_cast<float *>(sidx + sort_cap(G, R));  // pick coordinates, in order
-    float *pky = pkx + kMaxRoundPicks;
-    float *pkz = pky + kMaxRoundPicks;
-    float *px = pkz + kMaxRoundPicks;
+    float *px = reinterpret_cast<float *>(sidx + sort_cap(G, R));
 
     // ---- prologue: tile metadata and LDS offsets (block prefix sum) ----
     const int per = (ntl + kBlock - 1) / kBlock;
@@ -255,6 +268,18 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
     float *pd = pz + npl;
     float *pdl = pd + npl;
     uint32_t *po = reinterpret_cast<uint32_t *>(pdl + npl);
+    // the carving must end inside the dynamic LDS the plan sized
+    if (reinterpret_cast<unsigned char *>(po + npl) - smem > (ptrdiff_t)a.lds_budget) {
+        if (tid == 0) {
+            set_status(&a.hdr->sample_status, RFPS_ERR_INTERNAL);
+            // the rest of the team must not wait for this workgroup
+            for (int par = 0; par < 2; ++par)
+                for (int w = 0; w < W; ++w)
+                    bstore<S>(board + ((size_t)par * G + rank) * kMaxSlotWords + w,
+                              (unsigned long long)kAbortEpoch << 32);
+        }
+        return false;
+    }
 
     // Seed and initial update (Sec. 3.3)
     {
@@ -292,102 +317,89 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         if (clocks)
             t_mark = wall_clock64();
         // =============== L: local lookahead on a private copy ===============
-        for (int lt = tid; lt < ntl; lt += kBlock) {
-            tkeyl[lt] = tkey[lt];
-            tthrl[lt] = tthr[lt];
-            tbestl[lt] = tbest[lt];
-            tflag[lt] = 0;
-        }
-        __syncthreads();
-        for (int s = 0; s <= R; ++s) {
-            // arg max over the local tile keys (key and tile travel together)
-            unsigned long long lk = 0;
-            uint32_t lt_best = 0;
-            for (int lt = tid; lt < ntl; lt += kBlock) {
-                const unsigned long long k = tkeyl[lt];
-                if (k > lk) {
-                    lk = k;
-                    lt_best = (uint32_t)lt;
-                }
+        // One wavefront runs the whole lookahead: the per-step reductions stay
+        // inside it and its LDS operations complete in order, so the steps
+        // need no workgroup barrier.  Lanes take tiles for the arg max and the
+        // sphere tests; a tile that the test keeps is updated by all lanes.
+        if (wave == 0) {
+            for (int lt = lane; lt < ntl; lt += kWave) {
+                tkeyl[lt] = tkey[lt];
+                tthrl[lt] = tthr[lt];
+                tbestl[lt] = tbest[lt];
+                tflag[lt] = 0;
             }
-            const unsigned long long wk = wave_max_u64(lk);
-            const unsigned long long hit = __ballot(lk == wk && wk != 0);
-            if (lane == 0) {
-                sh.red[wave] = wk;
-                sh.redi[wave] =
-                    hit ? (uint32_t)__builtin_amdgcn_readlane((int)lt_best, __ffsll((long long)hit) - 1) : 0u;
-            }
-            __syncthreads();
-            unsigned long long bk = 0;
-            uint32_t bt = 0;
-#pragma unroll
-            for (int q = 0; q < kWavesPerBlock; ++q) {
-                if (sh.red[q] > bk) {
-                    bk = sh.red[q];
-                    bt = sh.redi[q];
-                }
-            }
-            if (s == R || bk == 0) {
-                // the bound (or an empty workgroup): no more local candidates
-                if (tid == 0) {
-                    sh.my[6 * R] = (uint32_t)(bk >> 32);
-                    sh.my[6 * R + 1] = (uint32_t)bk;
-                    for (int q = s; q < R; ++q)
-                        for (int w = 0; w < 6; ++w)
-                            sh.my[6 * q + w] = 0;
-                }
-                break;
-            }
-            const uint32_t p = tbestl[bt];
-            const float lx = px[p], ly = py[p], lz = pz[p];
-            if (tid == 0) {
-                sh.my[6 * s + 0] = __float_as_uint(lx);
-                sh.my[6 * s + 1] = __float_as_uint(ly);
-                sh.my[6 * s + 2] = __float_as_uint(lz);
-                sh.my[6 * s + 3] = __float_as_uint(pd[p]);
-                sh.my[6 * s + 4] = po[p];
-                sh.my[6 * s + 5] = (uint32_t)(bk >> 32);
-            }
-            // local update with l_s (pruned against the local thresholds)
-            for (int lt = tid; lt < ntl; lt += kBlock) {
-                const float q = sqdist(tcx[lt], tcy[lt], tcz[lt], lx, ly, lz);
-                if (!(q >= tthrl[lt]))
-                    tlist[atomicAdd(&sh.list_n, 1u)] = (uint32_t)lt;
-            }
-            __syncthreads();
-            const uint32_t nlist = sh.list_n;
-            for (uint32_t e = wave; e < nlist; e += kWavesPerBlock) {
-                const uint32_t lt = tlist[e];
-                const uint32_t meta = tmeta[lt];
-                const uint32_t ls = meta & 0xffffu, cnt = meta >> 16;
-                const bool valid = (uint32_t)lane < cnt;
-                const uint32_t pp = ls + (valid ? lane : 0);
-                if (!tflag[lt]) {
-                    if (valid)
-                        pdl[pp] = pd[pp];
-                }
-                float d = pdl[pp];
-                bool upd = false;
-                if (valid) {
-                    const float dx = px[pp] - lx, dy = py[pp] - ly, dz = pz[pp] - lz;
-                    const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-                    const bool skip = use_skip && (xx >= d || yy >= d || zz >= d);
-                    const float s2 = xx + yy;
-                    const float t = s2 + zz;
-                    upd = !skip && t < d;
-                    if (upd) {
-                        d = t;
-                        pdl[pp] = t;
+            for (int s = 0; s <= R; ++s) {
+                // arg max over the local tile keys (key and tile travel together)
+                unsigned long long lk = 0;
+                uint32_t lt_best = 0;
+                for (int lt = lane; lt < ntl; lt += kWave) {
+                    const unsigned long long k = tkeyl[lt];
+                    if (k > lk) {
+                        lk = k;
+                        lt_best = (uint32_t)lt;
                     }
                 }
-                if (lane == 0)
-                    tflag[lt] = 1;
-                if (__ballot(upd))
-                    tile_rekey(lane, lt, ls, cnt, pdl, po, trad, tkeyl, tbestl, tthrl);
+                const unsigned long long bk = wave_max_u64(lk);
+                const unsigned long long hit = __ballot(lk == bk && bk != 0);
+                if (s == R || bk == 0) {
+                    // the bound (or an empty workgroup): no more local candidates
+                    if (lane == 0) {
+                        sh.my[6 * R] = (uint32_t)(bk >> 32);
+                        sh.my[6 * R + 1] = (uint32_t)bk;
+                        for (int q = s; q < R; ++q)
+                            for (int w = 0; w < 6; ++w)
+                                sh.my[6 * q + w] = 0;
+                    }
+                    break;
+                }
+                const uint32_t bt = (uint32_t)__builtin_amdgcn_readlane((int)lt_best, __ffsll((long long)hit) - 1);
+                const uint32_t p = tbestl[bt];
+                const float lx = px[p], ly = py[p], lz = pz[p];
+                if (lane == 0) {
+                    sh.my[6 * s + 0] = __float_as_uint(lx);
+                    sh.my[6 * s + 1] = __float_as_uint(ly);
+                    sh.my[6 * s + 2] = __float_as_uint(lz);
+                    sh.my[6 * s + 3] = __float_as_uint(pd[p]);
+                    sh.my[6 * s + 4] = po[p];
+                    sh.my[6 * s + 5] = (uint32_t)(bk >> 32);
+                }
+                // local update with l_s (pruned against the local thresholds)
+                for (int lt0 = 0; lt0 < ntl; lt0 += kWave) {
+                    const int lt = lt0 + lane;
+                    const bool keep = lt < ntl && !(sqdist(tcx[lt], tcy[lt], tcz[lt], lx, ly, lz) >= tthrl[lt]);
+                    unsigned long long m = __ballot(keep);
+                    while (m) {
+                        const int t = lt0 + (__ffsll((long long)m) - 1);
+                        m &= m - 1;
+                        const uint32_t meta = tmeta[t];
+                        const uint32_t ls = meta & 0xffffu, cnt = meta >> 16;
+                        const bool valid = (uint32_t)lane < cnt;
+                        const uint32_t pp = ls + (valid ? lane : 0);
+                        if (!tflag[t]) {
+                            if (valid)
+                                pdl[pp] = pd[pp];
+                        }
+                        float d = pdl[pp];
+                        bool upd = false;
+                        if (valid) {
+                            const float dx = px[pp] - lx, dy = py[pp] - ly, dz = pz[pp] - lz;
+                            const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+                            const bool skip = use_skip && (xx >= d || yy >= d || zz >= d);
+                            const float s2 = xx + yy;
+                            const float tt = s2 + zz;
+                            upd = !skip && tt < d;
+                            if (upd) {
+                                d = tt;
+                                pdl[pp] = tt;
+                            }
+                        }
+                        if (lane == 0)
+                            tflag[t] = 1;
+                        if (__ballot(upd))
+                            tile_rekey(lane, t, ls, cnt, pdl, po, trad, tkeyl, tbestl, tthrl);
+                    }
+                }
             }
-            __syncthreads();
-            if (tid == 0)
-                sh.list_n = 0;
         }
         __syncthreads();
         if (clocks) {
@@ -425,6 +437,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 sh.abort = 1;
         }
         __syncthreads();
+        if (clocks)
+            tl.ph[4] += wall_clock64() - t_mark;
         if (!sh.abort) {
             const int total = G * W;
             const unsigned long long *sbase = board + (size_t)(epoch & 1u) * G * kMaxSlotWords;
@@ -433,47 +447,67 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             for (int r = 0; r < W; ++r)
                 pend |= (tid + kBlock * r < total) ? (1ull << r) : 0ull;
             bool ab = false;
-            constexpr int kChunk = 8;  // loads in flight per thread
+            // stores one word of a slot into the candidate arrays; false while
+            // the word does not carry the round's epoch yet
+            auto take = [&](int r, unsigned long long xr) -> bool {
+                const uint32_t ep = (uint32_t)(xr >> 32);
+                ab |= ep == kAbortEpoch;
+                if (ep != epoch)
+                    return false;
+                const int e = tid + kBlock * r, g = e / W, w = e % W;
+                const uint32_t v = (uint32_t)xr;
+                if (w < 6 * R) {
+                    // field f of candidate w / 6: x, y, z, true d2, index, local
+                    // d2; the arrays sit in LDS in the order cx, cy, cz, ctd,
+                    // cld, corig, G * R words apart
+                    const int f = w % 6;
+                    reinterpret_cast<uint32_t *>(cx)[(f ^ (f >> 2)) * (G * R) + g * R + w / 6] = v;
+                } else {
+                    // the bound key: high half first (little-endian halves)
+                    reinterpret_cast<uint32_t *>(bkey + g * (R + 1) + R)[w == 6 * R ? 1 : 0] = v;
+                }
+                return true;
+            };
+            auto word = [&](int r) {
+                const int e = tid + kBlock * r;
+                return sbase + (size_t)(e / W) * kMaxSlotWords + e % W;
+            };
+            // one pass with every load in flight at once (at most 32 per thread)
+            constexpr int kFast = W < 32 ? W : 32;
+            binvalidate<S>();
+#pragma unroll
+            for (int r0 = 0; r0 < W; r0 += kFast) {
+                unsigned long long x[kFast];
+#pragma unroll
+                for (int q = 0; q < kFast; ++q) {
+                    const int r = r0 + q;
+                    x[q] = (r < W && ((pend >> r) & 1ull)) ? bload<S>(word(r)) : 0ull;
+                }
+#pragma unroll
+                for (int q = 0; q < kFast; ++q) {
+                    const int r = r0 + q;
+                    if (r < W && ((pend >> r) & 1ull) && take(r, x[q]))
+                        pend &= ~(1ull << r);
+                }
+            }
+            // words not yet visible (rare): poll them in small groups
+            constexpr int kChunk = 8;
             for (uint32_t spin = 0; pend && !ab && spin < kSpinLimit; ++spin) {
                 binvalidate<S>();
 #pragma unroll 1
                 for (int r0 = 0; r0 < W; r0 += kChunk) {
-                unsigned long long x[kChunk];
+                    unsigned long long x[kChunk];
 #pragma unroll
-                for (int q = 0; q < kChunk; ++q) {
-                    const int r = r0 + q, e = tid + kBlock * r;
-                    x[q] = (r < W && ((pend >> r) & 1ull))
-                               ? bload<S>(sbase + (size_t)(e / W) * kMaxSlotWords + e % W)
-                               : 0ull;
-                }
-#pragma unroll
-                for (int q = 0; q < kChunk; ++q) {
-                    const int r = r0 + q;
-                    if (r >= W || !((pend >> r) & 1ull))
-                        continue;
-                    const unsigned long long xr = x[q];
-                    const uint32_t ep = (uint32_t)(xr >> 32);
-                    ab |= ep == kAbortEpoch;
-                    if (ep != epoch)
-                        continue;
-                    pend &= ~(1ull << r);
-                    const int e = tid + kBlock * r, g = e / W, w = e % W;
-                    const uint32_t v = (uint32_t)xr;
-                    if (w < 6 * R) {
-                        const int c = g * R + w / 6;
-                        switch (w % 6) {
-                        case 0: cx[c] = __uint_as_float(v); break;
-                        case 1: cy[c] = __uint_as_float(v); break;
-                        case 2: cz[c] = __uint_as_float(v); break;
-                        case 3: ctd[c] = __uint_as_float(v); break;
-                        case 4: corig[c] = v; break;
-                        default: cld[c] = __uint_as_float(v); break;
-                        }
-                    } else {
-                        // the bound key: high half first (little-endian halves)
-                        reinterpret_cast<uint32_t *>(bkey + g * (R + 1) + R)[w == 6 * R ? 1 : 0] = v;
+                    for (int q = 0; q < kChunk; ++q) {
+                        const int r = r0 + q;
+                        x[q] = (r < W && ((pend >> r) & 1ull)) ? bload<S>(word(r)) : 0ull;
                     }
-                }
+#pragma unroll
+                    for (int q = 0; q < kChunk; ++q) {
+                        const int r = r0 + q;
+                        if (r < W && ((pend >> r) & 1ull) && take(r, x[q]))
+                            pend &= ~(1ull << r);
+                    }
                 }
             }
             if (pend)
@@ -518,7 +552,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         // with the largest bound B_g at every step visits exactly this order
         // until the largest published bound S* = max_g k_{R+1} is reached,
         // where it stops as well; so the candidates above S* are compacted,
-        // sorted (bitonic, in LDS) and certified 64 positions at a time.
+        // put in order by counting and certified 64 positions at a time.
         {
             unsigned long long sk = 0;
             for (int g = tid; g < G; g += kBlock)
@@ -539,70 +573,95 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             // bound equals those candidates.  A group's candidates precede its
             // own bound, so a candidate equal to S* is taken when S* is the
             // bound of its own group.
-            for (int c = tid; c < G * R; c += kBlock) {
-                const int g = c / R;
-                const unsigned long long k = bkey[g * (R + 1) + c % R];
-                if (k > smax || (k == smax && bkey[g * (R + 1) + R] == smax))
-                    sidx[atomicAdd(&sh.mcount, 1u)] = (uint32_t)c;
+            for (int c0 = 0; c0 < G * R; c0 += kBlock) {
+                const int c = c0 + tid, g = c / R;
+                const unsigned long long k = c < G * R ? bkey[g * (R + 1) + c % R] : 0ull;
+                const bool keep = c < G * R && (k > smax || (k == smax && bkey[g * (R + 1) + R] == smax));
+                const unsigned long long bm = __ballot(keep);
+                uint32_t wbase = 0;
+                if (lane == 0 && bm)
+                    wbase = atomicAdd(&sh.mcount, (uint32_t)__popcll(bm));
+                wbase = (uint32_t)__shfl((int)wbase, 0, kWave);
+                if (keep) {
+                    const uint32_t pos = wbase + (uint32_t)__popcll(bm & (lane ? (~0ull >> (kWave - lane)) : 0ull));
+                    skey[pos] = k;
+                    sidx[pos] = (uint32_t)c;
+                }
             }
             __syncthreads();
             const uint32_t L = sh.mcount;
-            uint32_t sn = kWave;
-            while (sn < L)
-                sn <<= 1;
-            for (uint32_t e = L + tid; e < sn; e += kBlock)
-                sidx[e] = 0xffffffffu;  // key 0: sorts last
-            __syncthreads();
-            for (uint32_t k = 2; k <= sn; k <<= 1) {
-                for (uint32_t h = k >> 1; h > 0; h >>= 1) {
-                    for (uint32_t q = tid; q < sn / 2; q += kBlock) {
-                        const uint32_t e = ((q & ~(h - 1)) << 1) | (q & (h - 1));
-                        const uint32_t f = e + h;
-                        const uint32_t ca = sidx[e], cb = sidx[f];
-                        const unsigned long long ka = ca == 0xffffffffu ? 0ull : bkey[(ca / R) * (R + 1) + ca % R];
-                        const unsigned long long kb = cb == 0xffffffffu ? 0ull : bkey[(cb / R) * (R + 1) + cb % R];
-                        if ((e & k) == 0 ? ka < kb : ka > kb) {
-                            sidx[e] = cb;
-                            sidx[f] = ca;
-                        }
-                    }
-                    __syncthreads();
+            // Merge order by counting: the rank of a candidate is the number
+            // of larger keys plus the number of equal keys (repeats of one
+            // point) earlier in the list.  Every thread keeps its candidates'
+            // keys in registers and reads the list once (broadcast reads).
+            uint32_t *ord = reinterpret_cast<uint32_t *>(bkey);  // bkey is not read again this round
+            auto rank_all = [&](auto per_thread) {
+                constexpr int U = decltype(per_thread)::value;
+                unsigned long long mk[U];
+                uint32_t rk[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t i = tid + kBlock * u;
+                    mk[u] = i < L ? skey[i] : 0ull;
+                    rk[u] = 0;
                 }
-            }
+#pragma unroll 4
+                for (uint32_t q = 0; q < L; ++q) {
+                    const unsigned long long kq = skey[q];
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        rk[u] += (kq > mk[u] || (kq == mk[u] && q < tid + kBlock * u)) ? 1u : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t i = tid + kBlock * u;
+                    if (i < L)
+                        ord[rk[u]] = sidx[i];
+                }
+            };
+            if (L <= kBlock)
+                rank_all(std::integral_constant<int, 1>());
+            else if (L <= 2 * kBlock)
+                rank_all(std::integral_constant<int, 2>());
+            else if (L <= 4 * kBlock)
+                rank_all(std::integral_constant<int, 4>());
+            else
+                rank_all(std::integral_constant<int, 8>());
+            __syncthreads();
             const uint32_t pmax = min(min(L, (uint32_t)kMaxRoundPicks), (uint32_t)(job.m - j));
+            // coordinates in merge order (those of the certified prefix are the picks)
+            for (uint32_t e = tid; e < pmax; e += kBlock) {
+                const uint32_t c = ord[e];
+                pkx[e] = cx[c];
+                pky[e] = cy[c];
+                pkz[e] = cz[c];
+            }
             uint32_t P = 0;
             for (uint32_t base = 0; base < pmax; base += kWave) {
                 const uint32_t n = min((uint32_t)kWave, pmax - base);
                 if (tid < (int)n)
-                    sh.cmin[tid] = __float_as_uint(ctd[sidx[base + tid]]);
+                    sh.cmin[tid] = __float_as_uint(ctd[ord[base + tid]]);
                 __syncthreads();
                 if ((uint32_t)lane < n) {
                     // distances to every earlier position, split over the waves
-                    const uint32_t e = base + lane, c = sidx[e];
-                    const float x = cx[c], y = cy[c], z = cz[c];
+                    const uint32_t e = base + lane;
+                    const float x = pkx[e], y = pky[e], z = pkz[e];
                     float t = INFINITY;
-                    for (uint32_t q = wave; q < e; q += kWavesPerBlock) {
-                        const uint32_t cq = sidx[q];
-                        t = fminf(t, sqdist(x, y, z, cx[cq], cy[cq], cz[cq]));
-                    }
+                    for (uint32_t q = wave; q < e; q += kWavesPerBlock)
+                        t = fminf(t, sqdist(x, y, z, pkx[q], pky[q], pkz[q]));
                     atomicMin(&sh.cmin[lane], __float_as_uint(t));
                 }
                 __syncthreads();
                 if (wave == 0) {
-                    const bool fail = (uint32_t)lane < n && __uint_as_float(sh.cmin[lane]) != cld[sidx[base + lane]];
+                    const bool fail = (uint32_t)lane < n && __uint_as_float(sh.cmin[lane]) != cld[ord[base + lane]];
                     const unsigned long long fm = __ballot(fail);
                     if (lane == 0)
                         sh.mfail = fm ? (uint32_t)(__ffsll((long long)fm) - 1) : n;
                 }
                 __syncthreads();
                 const uint32_t ok = sh.mfail;
-                if (tid < (int)ok) {
-                    const uint32_t c = sidx[base + tid];
-                    pkx[base + tid] = cx[c];
-                    pky[base + tid] = cy[c];
-                    pkz[base + tid] = cz[c];
-                    ctd[c] = __uint_as_float(sh.cmin[tid]);  // the distance at selection
-                }
+                if (tid < (int)ok)
+                    ctd[ord[base + tid]] = __uint_as_float(sh.cmin[tid]);  // the distance at selection
                 P = base + ok;
                 __syncthreads();
                 if (ok < n)
@@ -612,7 +671,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 sh.npick = P;
             if (rank == 0) {
                 for (uint32_t k = tid; k < P; k += kBlock) {
-                    const uint32_t c = sidx[k];
+                    const uint32_t c = ord[k];
                     job.out_idx[j + k] = (int32_t)corig[c];
                     if (job.out_d2)
                         job.out_d2[j + k] = ctd[c];
@@ -642,56 +701,56 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             break;
 
         // =============== A: apply the round's picks to the true state ===============
-        for (int lt = tid; lt < ntl; lt += kBlock) {
+        // Each wavefront takes whole tiles.  Its lanes test the tile's sphere
+        // against 64 picks at a time (against the round-start threshold, which
+        // only the tile's own update can lower); the picks that survive update
+        // the tile's points, in pick order.
+        for (int lt = wave; lt < ntl; lt += kWavesPerBlock) {
             const float thr = tthr[lt];
             const float ccx = tcx[lt], ccy = tcy[lt], ccz = tcz[lt];
-            int k = 0;
-            for (; k < P; ++k) {
-                const float q = sqdist(ccx, ccy, ccz, pkx[k], pky[k], pkz[k]);
-                if (!(q >= thr))
-                    break;
-            }
-            if (tele) {
-                tl.tests += (k < P) ? (unsigned long long)(k + 1) : (unsigned long long)P;
-                tl.pruned += (unsigned long long)k;
-            }
-            if (k < P)
-                tlist[atomicAdd(&sh.list_n, 1u)] = (uint32_t)lt | ((uint32_t)k << 20);
-        }
-        __syncthreads();
-        const uint32_t nlist = sh.list_n;
-        for (uint32_t e = wave; e < nlist; e += kWavesPerBlock) {
-            const uint32_t lt = tlist[e] & 0xfffffu;
-            const int k0 = (int)(tlist[e] >> 20);
             const uint32_t meta = tmeta[lt];
             const uint32_t ls = meta & 0xffffu, cnt = meta >> 16;
             const bool valid = (uint32_t)lane < cnt;
             const uint32_t pp = ls + (valid ? lane : 0);
-            const float thr = tthr[lt];
-            const float ccx = tcx[lt], ccy = tcy[lt], ccz = tcz[lt];
-            const float x = px[pp], y = py[pp], z = pz[pp];
-            float d = pd[pp];
-            bool changed = false;
-            for (int k = k0; k < P; ++k) {
-                const float sx = pkx[k], sy = pky[k], sz = pkz[k];
-                if (k > k0 && sqdist(ccx, ccy, ccz, sx, sy, sz) >= thr)
-                    continue;  // uniform across the wave
+            float x = 0.0f, y = 0.0f, z = 0.0f, d = 0.0f;
+            bool loaded = false, changed = false;
+            for (int kb = 0; kb < P; kb += kWave) {
+                const int k = kb + lane;
+                const bool hit = k < P && !(sqdist(ccx, ccy, ccz, pkx[k], pky[k], pkz[k]) >= thr);
+                unsigned long long mask = __ballot(hit);
                 if (tele && lane == 0) {
-                    tl.visited += cnt;
-                    tl.tests += (k > k0);
+                    const unsigned long long nk = (unsigned long long)min(kWave, P - kb);
+                    const unsigned long long nh = (unsigned long long)__popcll(mask);
+                    tl.tests += nk;
+                    tl.pruned += nk - nh;
+                    tl.visited += nh * cnt;
                 }
-                if (valid) {
-                    const float dx = x - sx, dy = y - sy, dz = z - sz;
-                    const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-                    const bool skip = use_skip && (xx >= d || yy >= d || zz >= d);
-                    const float s2 = xx + yy;
-                    const float t = s2 + zz;
-                    if (!skip && t < d) {
-                        d = t;
-                        changed = true;
+                if (!mask)
+                    continue;
+                if (!loaded) {
+                    x = px[pp];
+                    y = py[pp];
+                    z = pz[pp];
+                    d = pd[pp];
+                    loaded = true;
+                }
+                while (mask) {
+                    const int kk = kb + (__ffsll((long long)mask) - 1);
+                    mask &= mask - 1;
+                    const float sx = pkx[kk], sy = pky[kk], sz = pkz[kk];
+                    if (valid) {
+                        const float dx = x - sx, dy = y - sy, dz = z - sz;
+                        const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+                        const bool skip = use_skip && (xx >= d || yy >= d || zz >= d);
+                        const float s2 = xx + yy;
+                        const float t = s2 + zz;
+                        if (!skip && t < d) {
+                            d = t;
+                            changed = true;
+                        }
+                        if (tele)
+                            tl.skipped += skip;
                     }
-                    if (tele)
-                        tl.skipped += skip;
                 }
             }
             if (changed)
@@ -729,16 +788,18 @@ __device__ void flush_telemetry(IndexHeader *hdr, const RoundTele &tl, bool cloc
         if (lane == 0 && s)
             atomicAdd(&hdr->tele[2 + q], s);
     }
-    if (clocks)
+    if (clocks) {
         for (int q = 0; q < 4; ++q)
             atomicAdd(&hdr->tele[kTeleTicksLookahead + q], tl.ph[q]);
+        atomicAdd(&hdr->tele[kTeleTicksWait], tl.ph[4]);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Single cloud: one team made of the whole grid, agent-scope exchange.
 // ---------------------------------------------------------------------------
 template <int R>
-__global__ __launch_bounds__(kBlock) void k_rfps_rounds(RoundArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rfps_rounds(RoundArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ RoundShared sh;
@@ -791,7 +852,7 @@ __device__ __forceinline__ uint32_t xcc_id()
 }
 
 template <int R>
-__global__ __launch_bounds__(kBlock) void k_rfps_rounds_batched(RoundArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rfps_rounds_batched(RoundArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ RoundShared sh;
