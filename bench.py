@@ -90,6 +90,7 @@ def main():
     ap.add_argument("--workload", default="dense_lidar", choices=sorted(WORKLOADS))
     ap.add_argument("--n-vox", type=int, default=0, help="voxel bins per axis (0 = library default)")
     ap.add_argument("--groups", type=int, default=0, help="sampler workgroups (0 = one per CU)")
+    ap.add_argument("--lookahead", type=int, default=0, help="candidates per workgroup per round (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparators", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=256, help="size of the copy kernel used to calibrate counters")
@@ -133,7 +134,7 @@ def main():
         idx = rf.build_index(x, n_vox=n_vox, reuse=idx)
         if with_sample_events is not None:
             with_sample_events[0].record(stream)
-        rf.sample(idx, M, 0, groups=args.groups, out_idx=out_i, out_d2=out_d)
+        rf.sample(idx, M, 0, groups=args.groups, lookahead=args.lookahead, out_idx=out_i, out_d2=out_d)
         if with_sample_events is not None:
             with_sample_events[1].record(stream)
 
@@ -173,7 +174,8 @@ def main():
     torch.cuda.synchronize()
     build_ms = b0.elapsed_time(b1)
     info = rf.read_index_info(idx)
-    rf.sample(idx, M, 0, groups=args.groups, flags=rf.F_TELEMETRY | rf.F_TRACE, out_idx=out_i, out_d2=out_d)
+    rf.sample(idx, M, 0, groups=args.groups, lookahead=args.lookahead, flags=rf.F_TELEMETRY | rf.F_TRACE,
+              out_idx=out_i, out_d2=out_d)
     tel = rf.read_telemetry(idx)
     tr, hz = rf.read_trace(idx)
     # per exchange round: (publish time, outcome time | picks << 48)
@@ -209,7 +211,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "n_points": N,
-                   "m": M, "start": 0, "n_vox": n_vox, "tile": 64,
+                   "m": M, "start": 0, "n_vox": n_vox, "tile": 64, "lookahead": args.lookahead or 4,
                    "groups": args.groups or torch.cuda.get_device_properties(dev).multi_processor_count},
         "ms_per_cloud": ms_per_step,
         "build_ms": build_ms,

@@ -189,6 +189,10 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 {
     const uint32_t hi = (uint32_t)(v >> 32);
     const uint32_t mhi = wave_max_u32(hi);
+    const unsigned long long tie = __ballot(hi == mhi);
+    if (__popcll(tie) == 1)  // one lane holds the largest high half: its low half goes with it
+        return ((unsigned long long)mhi << 32) |
+               (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, __ffsll((long long)tie) - 1);
     const uint32_t mlo = wave_max_u32(hi == mhi ? (uint32_t)v : 0u);
     return ((unsigned long long)mhi << 32) | mlo;
 }
@@ -270,7 +274,9 @@ __device__ __forceinline__ float prune_threshold(float R, float dv)
         return 0.0f;
     if (!(dv >= 0x1p-100f) || !(dv <= 0x1p100f))
         return __uint_as_float(0x7fc00000u);
-    double q = (double)R + sqrt((double)dv / (1.0 - 0x1p-20));
+    // dv * (1 + 2^-19) >= dv / (1 - 2^-20); the product's rounding is covered
+    // by the 2^-50 factors below, like the square root's and the sum's
+    double q = (double)R + sqrt((double)dv * (1.0 + 0x1p-19));
     q *= 1.0 + 0x1p-50;
     double T = q * q * (1.0 + 0x1p-50);
     double t64 = T * (1.0 + 0x1p-20);

@@ -165,8 +165,10 @@ struct RoundShared {
     unsigned long long red[kWavesPerBlock];
     uint32_t redi[kWavesPerBlock];
     uint32_t scan[kWavesPerBlock];
-    uint32_t abort, list_n, npick, mcount, mfail;
+    unsigned long long red2[kWavesPerBlock];
+    uint32_t abort, list_n, npick, mcount, mback, mfail, mtotal, msel;
     uint32_t cmin[kWave];  // merge: true distances of one chunk of 64 positions (float bits)
+    uint32_t hist[256];    // merge: candidates per key bucket
     uint32_t my[6 * 8 + 2];  // this workgroup's slot payload (R <= 8)
 };
 
@@ -554,118 +556,244 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         // where it stops as well; so the candidates above S* are compacted,
         // put in order by counting and certified 64 positions at a time.
         {
-            unsigned long long sk = 0;
-            for (int g = tid; g < G; g += kBlock)
+            unsigned long long sk = 0, hk = 0;
+            for (int g = tid; g < G; g += kBlock) {
                 sk = umax64(sk, bkey[g * (R + 1) + R]);
+                hk = umax64(hk, bkey[g * (R + 1)]);
+            }
             sk = wave_max_u64(sk);
-            if (lane == 0)
+            hk = wave_max_u64(hk);
+            if (lane == 0) {
                 sh.red[wave] = sk;
-            if (tid == 0)
+                sh.red2[wave] = hk;
+            }
+            if (tid == 0) {
                 sh.mcount = 0;
+                sh.mback = 0;
+            }
+            sh.hist[tid] = 0;
             __syncthreads();
-            unsigned long long smax = 0;
+            unsigned long long smax = 0, hmax = 0;
 #pragma unroll
-            for (int q = 0; q < kWavesPerBlock; ++q)
+            for (int q = 0; q < kWavesPerBlock; ++q) {
                 smax = umax64(smax, sh.red[q]);
+                hmax = umax64(hmax, sh.red2[q]);
+            }
             // Keys of different points differ, so only a group's own repeats
             // can tie: once every point of a group has local distance 0, its
             // lookahead returns its lowest index again and again, and its
             // bound equals those candidates.  A group's candidates precede its
             // own bound, so a candidate equal to S* is taken when S* is the
             // bound of its own group.
+            auto taken = [&](int c, unsigned long long &k) {
+                const int g = c / R;
+                k = c < G * R ? bkey[g * (R + 1) + c % R] : 0ull;
+                return c < G * R && (k > smax || (k == smax && bkey[g * (R + 1) + R] == smax));
+            };
+            // Only the first few positions of the order are usually needed:
+            // a histogram of the keys' high halves (distance bits, between S*
+            // and the largest key) finds a bucket above which at least
+            // kSelect candidates lie; those come first in the list and are put
+            // in order alone, the rest only if the round gets that far.
+            constexpr uint32_t kSelect = 128;
+            const uint32_t hlo = (uint32_t)(smax >> 32);
+            const uint32_t span = (uint32_t)(hmax >> 32) - hlo;
+            const int bits = span ? 32 - __clz((int)span) : 0;
+            const int bshift = bits > 8 ? bits - 8 : 0;
+            auto bucket = [&](unsigned long long k) { return ((uint32_t)(k >> 32) - hlo) >> bshift; };
             for (int c0 = 0; c0 < G * R; c0 += kBlock) {
-                const int c = c0 + tid, g = c / R;
-                const unsigned long long k = c < G * R ? bkey[g * (R + 1) + c % R] : 0ull;
-                const bool keep = c < G * R && (k > smax || (k == smax && bkey[g * (R + 1) + R] == smax));
-                const unsigned long long bm = __ballot(keep);
-                uint32_t wbase = 0;
-                if (lane == 0 && bm)
-                    wbase = atomicAdd(&sh.mcount, (uint32_t)__popcll(bm));
-                wbase = (uint32_t)__shfl((int)wbase, 0, kWave);
+                unsigned long long k;
+                if (taken(c0 + tid, k))
+                    atomicAdd(&sh.hist[bucket(k)], 1u);
+            }
+            __syncthreads();
+            if (wave == 0) {
+                uint32_t c4 = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    c4 += sh.hist[4 * lane + b];
+                uint32_t suf = c4;  // candidates in the buckets of lanes >= this one
+#pragma unroll
+                for (int off = 1; off < kWave; off <<= 1) {
+                    const uint32_t o = (uint32_t)__shfl_down((int)suf, off, kWave);
+                    suf += lane + off < kWave ? o : 0u;
+                }
+                const uint32_t total = (uint32_t)__shfl((int)suf, 0, kWave);
+                const unsigned long long enough = __ballot(suf >= kSelect);
+                const int lt = enough ? 63 - __clzll((long long)enough) : -1;
+                if (lane == 0) {
+                    sh.mtotal = total;
+                    sh.msel = 0;  // everything
+                }
+                if (total > kSelect && lane == lt) {
+                    uint32_t acc = suf - c4;
+                    for (int b = 3; b >= 0; --b) {
+                        acc += sh.hist[4 * lane + b];
+                        if (acc >= kSelect) {
+                            sh.msel = (uint32_t)(4 * lane + b);
+                            break;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            const uint32_t L = sh.mtotal, bsel = sh.msel;
+            for (int c0 = 0; c0 < G * R; c0 += kBlock) {
+                const int c = c0 + tid;
+                unsigned long long k;
+                const bool keep = taken(c, k);
+                const bool front = keep && bucket(k) >= bsel;
+                const unsigned long long fm = __ballot(front), bm = __ballot(keep && !front);
+                uint32_t fbase = 0, bbase = 0;
+                if (lane == 0) {
+                    if (fm)
+                        fbase = atomicAdd(&sh.mcount, (uint32_t)__popcll(fm));
+                    if (bm)
+                        bbase = atomicAdd(&sh.mback, (uint32_t)__popcll(bm));
+                }
+                fbase = (uint32_t)__shfl((int)fbase, 0, kWave);
+                bbase = (uint32_t)__shfl((int)bbase, 0, kWave);
+                const unsigned long long below = lane ? (~0ull >> (kWave - lane)) : 0ull;
                 if (keep) {
-                    const uint32_t pos = wbase + (uint32_t)__popcll(bm & (lane ? (~0ull >> (kWave - lane)) : 0ull));
+                    const uint32_t pos = front ? fbase + (uint32_t)__popcll(fm & below)
+                                               : L - 1 - (bbase + (uint32_t)__popcll(bm & below));
                     skey[pos] = k;
                     sidx[pos] = (uint32_t)c;
                 }
             }
+            if (tid < kWave)
+                sh.cmin[tid] = 0x7f800000u;  // +inf: the chunk minima start here
             __syncthreads();
-            const uint32_t L = sh.mcount;
-            // Merge order by counting: the rank of a candidate is the number
-            // of larger keys plus the number of equal keys (repeats of one
-            // point) earlier in the list.  Every thread keeps its candidates'
-            // keys in registers and reads the list once (broadcast reads).
+            const uint32_t Lf = sh.mcount;  // the front part: keys above every key behind it
+            // Order by counting: the rank of a candidate within a part of the
+            // list is the number of larger keys plus the number of equal keys
+            // (repeats of one point) earlier in the part.  Every thread keeps
+            // its candidates' keys in registers and reads the part once.
             uint32_t *ord = reinterpret_cast<uint32_t *>(bkey);  // bkey is not read again this round
-            auto rank_all = [&](auto per_thread) {
+            auto rank_part = [&](auto per_thread, uint32_t lo, uint32_t hi, auto key_at) {
                 constexpr int U = decltype(per_thread)::value;
                 unsigned long long mk[U];
                 uint32_t rk[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const uint32_t i = tid + kBlock * u;
-                    mk[u] = i < L ? skey[i] : 0ull;
+                    const uint32_t i = lo + tid + kBlock * u;
+                    mk[u] = i < hi ? key_at(i) : 0ull;
                     rk[u] = 0;
                 }
-#pragma unroll 4
-                for (uint32_t q = 0; q < L; ++q) {
-                    const unsigned long long kq = skey[q];
+                auto count = [&](uint32_t q, unsigned long long kq) {
 #pragma unroll
                     for (int u = 0; u < U; ++u)
-                        rk[u] += (kq > mk[u] || (kq == mk[u] && q < tid + kBlock * u)) ? 1u : 0u;
+                        rk[u] += (kq > mk[u] || (kq == mk[u] && q < lo + tid + kBlock * u)) ? 1u : 0u;
+                };
+                uint32_t q0 = lo;
+                for (; q0 + 8 <= hi; q0 += 8) {
+                    unsigned long long kq[8];
+#pragma unroll
+                    for (int v = 0; v < 8; ++v)
+                        kq[v] = key_at(q0 + v);
+#pragma unroll
+                    for (int v = 0; v < 8; ++v)
+                        count(q0 + v, kq[v]);
                 }
+                for (; q0 < hi; ++q0)
+                    count(q0, key_at(q0));
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const uint32_t i = tid + kBlock * u;
-                    if (i < L)
-                        ord[rk[u]] = sidx[i];
+                    const uint32_t i = lo + tid + kBlock * u;
+                    if (i < hi)
+                        ord[lo + rk[u]] = sidx[i];
                 }
             };
-            if (L <= kBlock)
-                rank_all(std::integral_constant<int, 1>());
-            else if (L <= 2 * kBlock)
-                rank_all(std::integral_constant<int, 2>());
-            else if (L <= 4 * kBlock)
-                rank_all(std::integral_constant<int, 4>());
-            else
-                rank_all(std::integral_constant<int, 8>());
-            __syncthreads();
+            auto rank_range = [&](uint32_t lo, uint32_t hi, auto key_at) {
+                const uint32_t n = hi - lo;
+                if (n <= kBlock)
+                    rank_part(std::integral_constant<int, 1>(), lo, hi, key_at);
+                else if (n <= 2 * kBlock)
+                    rank_part(std::integral_constant<int, 2>(), lo, hi, key_at);
+                else if (n <= 4 * kBlock)
+                    rank_part(std::integral_constant<int, 4>(), lo, hi, key_at);
+                else
+                    rank_part(std::integral_constant<int, 8>(), lo, hi, key_at);
+                __syncthreads();
+            };
+            rank_range(0, Lf, [&](uint32_t i) { return skey[i]; });
             const uint32_t pmax = min(min(L, (uint32_t)kMaxRoundPicks), (uint32_t)(job.m - j));
-            // coordinates in merge order (those of the certified prefix are the picks)
-            for (uint32_t e = tid; e < pmax; e += kBlock) {
-                const uint32_t c = ord[e];
-                pkx[e] = cx[c];
-                pky[e] = cy[c];
-                pkz[e] = cz[c];
-            }
-            uint32_t P = 0;
-            for (uint32_t base = 0; base < pmax; base += kWave) {
-                const uint32_t n = min((uint32_t)kWave, pmax - base);
-                if (tid < (int)n)
-                    sh.cmin[tid] = __float_as_uint(ctd[ord[base + tid]]);
-                __syncthreads();
-                if ((uint32_t)lane < n) {
-                    // distances to every earlier position, split over the waves
-                    const uint32_t e = base + lane;
-                    const float x = pkx[e], y = pky[e], z = pkz[e];
-                    float t = INFINITY;
-                    for (uint32_t q = wave; q < e; q += kWavesPerBlock)
-                        t = fminf(t, sqdist(x, y, z, pkx[q], pky[q], pkz[q]));
-                    atomicMin(&sh.cmin[lane], __float_as_uint(t));
+            // certifies positions [from, lim) of the order; returns the end of
+            // the certified prefix
+            auto certify = [&](uint32_t from, uint32_t lim) -> uint32_t {
+                // coordinates in merge order (those of the certified prefix are the picks)
+                for (uint32_t e = from + tid; e < lim; e += kBlock) {
+                    const uint32_t c = ord[e];
+                    pkx[e] = cx[c];
+                    pky[e] = cy[c];
+                    pkz[e] = cz[c];
                 }
                 __syncthreads();
-                if (wave == 0) {
-                    const bool fail = (uint32_t)lane < n && __uint_as_float(sh.cmin[lane]) != cld[ord[base + lane]];
-                    const unsigned long long fm = __ballot(fail);
-                    if (lane == 0)
-                        sh.mfail = fm ? (uint32_t)(__ffsll((long long)fm) - 1) : n;
+                uint32_t P = from;
+                for (uint32_t base = from; base < lim; base += kWave) {
+                    const uint32_t n = min((uint32_t)kWave, lim - base);
+                    // true distance of every position of the chunk: its round-start
+                    // value, lowered by every earlier position (the earlier ones
+                    // are all picks if this one is reached); wave w takes the
+                    // earlier positions q = w mod 4 (broadcast reads)
+                    {
+                        const uint32_t e = base + lane;
+                        const bool in = (uint32_t)lane < n;
+                        const float x = pkx[in ? e : base], y = pky[in ? e : base], z = pkz[in ? e : base];
+                        float t = in ? ctd[ord[e]] : INFINITY;
+                        const uint32_t qend = base + n - 1;  // no position reaches past it
+                        uint32_t q = wave;
+                        for (; q + 3 * kWavesPerBlock < qend; q += 4 * kWavesPerBlock) {
+                            float sx[4], sy[4], sz[4];
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                sx[v] = pkx[q + v * kWavesPerBlock];
+                                sy[v] = pky[q + v * kWavesPerBlock];
+                                sz[v] = pkz[q + v * kWavesPerBlock];
+                            }
+#pragma unroll
+                            for (int v = 0; v < 4; ++v)
+                                if (q + v * kWavesPerBlock < e)
+                                    t = fminf(t, sqdist(x, y, z, sx[v], sy[v], sz[v]));
+                        }
+                        for (; q < qend; q += kWavesPerBlock)
+                            if (q < e)
+                                t = fminf(t, sqdist(x, y, z, pkx[q], pky[q], pkz[q]));
+                        if (in)
+                            atomicMin(&sh.cmin[lane], __float_as_uint(t));
+                    }
+                    __syncthreads();
+                    if (wave == 0) {
+                        const bool fail =
+                            (uint32_t)lane < n && __uint_as_float(sh.cmin[lane]) != cld[ord[base + lane]];
+                        const unsigned long long fm = __ballot(fail);
+                        if (lane == 0)
+                            sh.mfail = fm ? (uint32_t)(__ffsll((long long)fm) - 1) : n;
+                    }
+                    __syncthreads();
+                    const uint32_t ok = sh.mfail;
+                    if (tid < (int)ok)
+                        ctd[ord[base + tid]] = __uint_as_float(sh.cmin[tid]);  // the distance at selection
+                    if (tid < kWave)
+                        sh.cmin[tid] = 0x7f800000u;  // +inf for the next chunk
+                    P = base + ok;
+                    __syncthreads();
+                    if (ok < n)
+                        break;
                 }
-                __syncthreads();
-                const uint32_t ok = sh.mfail;
-                if (tid < (int)ok)
-                    ctd[ord[base + tid]] = __uint_as_float(sh.cmin[tid]);  // the distance at selection
-                P = base + ok;
-                __syncthreads();
-                if (ok < n)
-                    break;
+                return P;
+            };
+            uint32_t P = certify(0, min(Lf, pmax));
+            if (P == Lf && P < pmax) {
+                // every position of the front part holds: order the part behind
+                // it (all its keys are smaller) and go on.  The staged pick
+                // coordinates share their words with the stored keys, so these
+                // keys are formed again from the candidates' distances and indices.
+                rank_range(Lf, L, [&](uint32_t i) {
+                    const uint32_t c = sidx[i];
+                    return ((unsigned long long)__float_as_uint(cld[c]) << 32) | (~corig[c]);
+                });
+                P = certify(P, pmax);
             }
             if (tid == 0)
                 sh.npick = P;
@@ -701,67 +829,73 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             break;
 
         // =============== A: apply the round's picks to the true state ===============
-        // Each wavefront takes whole tiles.  Its lanes test the tile's sphere
-        // against 64 picks at a time (against the round-start threshold, which
-        // only the tile's own update can lower); the picks that survive update
-        // the tile's points, in pick order.
-        for (int lt = wave; lt < ntl; lt += kWavesPerBlock) {
-            const float thr = tthr[lt];
-            const float ccx = tcx[lt], ccy = tcy[lt], ccz = tcz[lt];
-            const uint32_t meta = tmeta[lt];
-            const uint32_t ls = meta & 0xffffu, cnt = meta >> 16;
-            const bool valid = (uint32_t)lane < cnt;
-            const uint32_t pp = ls + (valid ? lane : 0);
-            float x = 0.0f, y = 0.0f, z = 0.0f, d = 0.0f;
-            bool loaded = false, changed = false;
-            for (int kb = 0; kb < P; kb += kWave) {
-                const int k = kb + lane;
-                const bool hit = k < P && !(sqdist(ccx, ccy, ccz, pkx[k], pky[k], pkz[k]) >= thr);
-                unsigned long long mask = __ballot(hit);
-                if (tele && lane == 0) {
-                    const unsigned long long nk = (unsigned long long)min(kWave, P - kb);
-                    const unsigned long long nh = (unsigned long long)__popcll(mask);
-                    tl.tests += nk;
-                    tl.pruned += nk - nh;
-                    tl.visited += nh * cnt;
-                }
-                if (!mask)
-                    continue;
-                if (!loaded) {
-                    x = px[pp];
-                    y = py[pp];
-                    z = pz[pp];
-                    d = pd[pp];
-                    loaded = true;
-                }
-                while (mask) {
-                    const int kk = kb + (__ffsll((long long)mask) - 1);
-                    mask &= mask - 1;
-                    const float sx = pkx[kk], sy = pky[kk], sz = pkz[kk];
-                    if (valid) {
-                        const float dx = x - sx, dy = y - sy, dz = z - sz;
-                        const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-                        const bool skip = use_skip && (xx >= d || yy >= d || zz >= d);
-                        const float s2 = xx + yy;
-                        const float t = s2 + zz;
-                        if (!skip && t < d) {
-                            d = t;
-                            changed = true;
-                        }
-                        if (tele)
-                            tl.skipped += skip;
+        // Lanes take picks (64 at a time), wavefronts take tiles, four at a
+        // time so that their sphere data is in flight together.  A tile's test
+        // uses its current threshold (only its own update can lower it); the
+        // picks that survive update the tile's points, in pick order.
+        for (int kb = 0; kb < P; kb += kWave) {
+            const int k = kb + lane;
+            const bool kin = k < P;
+            const float sx = kin ? pkx[k] : 0.0f, sy = kin ? pky[k] : 0.0f, sz = kin ? pkz[k] : 0.0f;
+            const unsigned long long nk = (unsigned long long)min(kWave, P - kb);
+            for (int lt0 = 4 * wave; lt0 < ntl; lt0 += 4 * kWavesPerBlock) {
+                unsigned long long m[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int lt = lt0 + v;
+                    const bool tin = lt < ntl;
+                    const int li = tin ? lt : 0;
+                    const float thr = tin ? tthr[li] : 0.0f;  // 0: every test prunes
+                    m[v] = __ballot(kin && !(sqdist(tcx[li], tcy[li], tcz[li], sx, sy, sz) >= thr));
+                    if (tele && lane == 0 && tin) {
+                        const unsigned long long nh = (unsigned long long)__popcll(m[v]);
+                        tl.tests += nk;
+                        tl.pruned += nk - nh;
+                        tl.visited += nh * (tmeta[li] >> 16);
                     }
                 }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    unsigned long long mask = m[v];
+                    if (!mask)
+                        continue;
+                    const int lt = lt0 + v;
+                    const uint32_t meta = tmeta[lt];
+                    const uint32_t ls = meta & 0xffffu, cnt = meta >> 16;
+                    const bool valid = (uint32_t)lane < cnt;
+                    const uint32_t pp = ls + (valid ? lane : 0);
+                    const float x = px[pp], y = py[pp], z = pz[pp];
+                    float d = pd[pp];
+                    bool changed = false;
+                    while (mask) {
+                        const int kk = kb + (__ffsll((long long)mask) - 1);
+                        mask &= mask - 1;
+                        const float qx = pkx[kk], qy = pky[kk], qz = pkz[kk];
+                        if (valid) {
+                            const float dx = x - qx, dy = y - qy, dz = z - qz;
+                            const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+                            const bool skip = use_skip && (xx >= d || yy >= d || zz >= d);
+                            const float s2 = xx + yy;
+                            const float t = s2 + zz;
+                            if (!skip && t < d) {
+                                d = t;
+                                changed = true;
+                            }
+                            if (tele)
+                                tl.skipped += skip;
+                        }
+                    }
+                    if (changed)
+                        pd[pp] = d;
+                    const unsigned long long um = __ballot(changed);
+                    if (tele && lane == 0) {
+                        tl.updated += (unsigned long long)__popcll(um);
+                        tl.resync += um != 0;
+                    }
+                    if (um)
+                        tile_rekey(lane, lt, ls, cnt, pd, po, trad, tkey, tbest, tthr);
+                }
             }
-            if (changed)
-                pd[pp] = d;
-            const unsigned long long um = __ballot(changed);
-            if (tele && lane == 0) {
-                tl.updated += (unsigned long long)__popcll(um);
-                tl.resync += um != 0;
-            }
-            if (um)
-                tile_rekey(lane, lt, ls, cnt, pd, po, trad, tkey, tbest, tthr);
         }
         __syncthreads();
         if (tid == 0)
