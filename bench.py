@@ -211,7 +211,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "n_points": N,
-                   "m": M, "start": 0, "n_vox": n_vox, "tile": 64, "lookahead": args.lookahead or 4,
+                   "m": M, "start": 0, "n_vox": n_vox, "tile": 64, "lookahead": args.lookahead or 2,
                    "groups": args.groups or torch.cuda.get_device_properties(dev).multi_processor_count},
         "ms_per_cloud": ms_per_step,
         "build_ms": build_ms,

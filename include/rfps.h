@@ -71,7 +71,7 @@ typedef struct rfps_params {
      * compute units (all must be resident at once); 0 = one per compute unit. */
     int32_t groups;
     /* Lookahead depth of the multi-pick sampler: every workgroup proposes
-     * this many local candidates per exchange round; 2, 4 or 8 (0 = 4).
+     * this many local candidates per exchange round; 2, 4 or 8 (0 = 2).
      * Output-neutral, like n_vox, tile and groups. */
     int32_t lookahead;
     /* RFPS_F_* bits. */
@@ -239,7 +239,7 @@ rfps_status rfps_read_plain_status(const void *ws, size_t ws_bytes, void *stream
  *             the same bins for every cloud; tile as for rfps_build_index;
  *             groups: workgroups per cloud (a divisor of the compute units of
  *             one XCD, at least 2; 0 = all of them); lookahead 2, 4 or 8 (0 =
- *             4).  RFPS_F_NO_PRUNE, RFPS_F_SINGLE_PICK and RFPS_F_TRACE are
+ *             2).  RFPS_F_NO_PRUNE, RFPS_F_SINGLE_PICK and RFPS_F_TRACE are
  *             not available here (RFPS_ERR_UNSUPPORTED).
  *   ws        device workspace of rfps_batched_workspace_size() bytes,
  *             256-byte aligned; calls on one workspace must not overlap.

@@ -19,7 +19,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr uint32_t kKnownFlags =
     RFPS_F_NO_PRUNE | RFPS_F_NO_POINT_SKIP | RFPS_F_TELEMETRY | RFPS_F_TRACE | RFPS_F_SINGLE_PICK;
-constexpr int kDefaultLookahead = 4;
+constexpr int kDefaultLookahead = 2;
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 

@@ -198,7 +198,10 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                              bool record_trace, bool clocks)
 {
     constexpr int W = 6 * R + 2;  // words per slot
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    // the wavefront index is uniform: as a scalar it keeps wave-strided loops
+    // and their addressing off the exec mask
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
     const uint32_t span = job.te - job.tb;
     const int ntl = (span > (uint32_t)rank) ? (int)((span - 1 - rank) / G) + 1 : 0;
     const bool use_skip = !(a.flags & RFPS_F_NO_POINT_SKIP);
@@ -838,15 +841,25 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             const bool kin = k < P;
             const float sx = kin ? pkx[k] : 0.0f, sy = kin ? pky[k] : 0.0f, sz = kin ? pkz[k] : 0.0f;
             const unsigned long long nk = (unsigned long long)min(kWave, P - kb);
+            const unsigned long long kmask = nk == kWave ? ~0ull : ((1ull << nk) - 1ull);
             for (int lt0 = 4 * wave; lt0 < ntl; lt0 += 4 * kWavesPerBlock) {
                 unsigned long long m[4];
+                float qx[4], qy[4], qz[4], qt[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int li = lt0 + v < ntl ? lt0 + v : lt0;
+                    qx[v] = tcx[li];
+                    qy[v] = tcy[li];
+                    qz[v] = tcz[li];
+                    qt[v] = tthr[li];
+                }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int lt = lt0 + v;
                     const bool tin = lt < ntl;
                     const int li = tin ? lt : 0;
-                    const float thr = tin ? tthr[li] : 0.0f;  // 0: every test prunes
-                    m[v] = __ballot(kin && !(sqdist(tcx[li], tcy[li], tcz[li], sx, sy, sz) >= thr));
+                    const bool keep = !(sqdist(qx[v], qy[v], qz[v], sx, sy, sz) >= qt[v]);
+                    m[v] = tin ? __ballot(keep) & kmask : 0ull;
                     if (tele && lane == 0 && tin) {
                         const unsigned long long nh = (unsigned long long)__popcll(m[v]);
                         tl.tests += nk;
