@@ -521,16 +521,34 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         __syncthreads();
         if (!sh.abort) {
             // candidate keys; a workgroup without tiles publishes the bound 0
-            // and no candidates
+            // and no candidates.  The merge's S* (largest bound) and largest
+            // head key are reduced on the way.
+            unsigned long long sk = 0, hk = 0;
             for (int g = tid; g < G; g += kBlock) {
-                const bool empty = bkey[g * (R + 1) + R] == 0ull;
+                const unsigned long long bound = bkey[g * (R + 1) + R];
+                const bool empty = bound == 0ull;
 #pragma unroll
                 for (int s2 = 0; s2 < R; ++s2) {
                     const int c = g * R + s2;
-                    bkey[g * (R + 1) + s2] =
+                    const unsigned long long k =
                         empty ? 0ull : ((unsigned long long)__float_as_uint(cld[c]) << 32) | (~corig[c]);
+                    bkey[g * (R + 1) + s2] = k;
+                    if (s2 == 0)
+                        hk = umax64(hk, k);
                 }
+                sk = umax64(sk, bound);
             }
+            sk = wave_max_u64(sk);
+            hk = wave_max_u64(hk);
+            if (lane == 0) {
+                sh.red[wave] = sk;
+                sh.red2[wave] = hk;
+            }
+            if (tid == 0) {
+                sh.mcount = 0;
+                sh.mback = 0;
+            }
+            sh.hist[tid] = 0;
         }
         __syncthreads();
         if (sh.abort) {
@@ -559,23 +577,6 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         // where it stops as well; so the candidates above S* are compacted,
         // put in order by counting and certified 64 positions at a time.
         {
-            unsigned long long sk = 0, hk = 0;
-            for (int g = tid; g < G; g += kBlock) {
-                sk = umax64(sk, bkey[g * (R + 1) + R]);
-                hk = umax64(hk, bkey[g * (R + 1)]);
-            }
-            sk = wave_max_u64(sk);
-            hk = wave_max_u64(hk);
-            if (lane == 0) {
-                sh.red[wave] = sk;
-                sh.red2[wave] = hk;
-            }
-            if (tid == 0) {
-                sh.mcount = 0;
-                sh.mback = 0;
-            }
-            sh.hist[tid] = 0;
-            __syncthreads();
             unsigned long long smax = 0, hmax = 0;
 #pragma unroll
             for (int q = 0; q < kWavesPerBlock; ++q) {
