@@ -13,8 +13,8 @@
 //      (on the private copy, with the same spherical pruning), giving local
 //      candidates l_1..l_R with local keys k_1 > .. > k_R and the bound
 //      k_{R+1}, the largest local key left after them;
-//   X  exchange: each workgroup publishes its candidates (coordinates, true
-//      round-start distance, local distance) and k_{R+1};
+//   X  exchange: each workgroup publishes its candidates (coordinates, local
+//      distance, original index) and k_{R+1};
 //   M  merge: every workgroup replays the same deterministic merge.  Group g
 //      keeps a head h_g (how many of its candidates were taken).  Its bound
 //      B_g = k_{h_g+1} is an upper bound on the true key of every point of g:
@@ -24,6 +24,9 @@
 //      the group with the largest bound still has its true key equal to its
 //      local key (no other pick of the round lowered it), that candidate is
 //      exactly the next FPS selection (the Sec. 3.1 rule; keys are unique).
+//      The local distance already includes the group's own earlier picks
+//      (those it skipped are at least as far), so the true distance is the
+//      local one lowered by the other groups' earlier picks;
 //      Otherwise the round ends.  This visits the candidates in descending
 //      order of local key, so the merge sorts them and certifies them in that
 //      order, all threads of the workgroup at once;
@@ -88,7 +91,7 @@ __host__ __device__ __forceinline__ uint32_t merge_words(uint32_t G, uint32_t R)
 
 __host__ __device__ __forceinline__ uint32_t rounds_lds_need(uint32_t tiles, uint32_t pts, uint32_t G, uint32_t R)
 {
-    return tiles * 60u + pts * 24u + G * R * 24u + G * (R + 1u) * 8u + sort_cap(G, R) * 4u + merge_words(G, R) * 4u +
+    return tiles * 60u + pts * 24u + G * R * 20u + G * (R + 1u) * 8u + sort_cap(G, R) * 4u + merge_words(G, R) * 4u +
            128u;
 }
 
@@ -169,7 +172,7 @@ struct RoundShared {
     uint32_t abort, list_n, npick, mcount, mback, mfail, mtotal, msel;
     uint32_t cmin[kWave];  // merge: true distances of one chunk of 64 positions (float bits)
     uint32_t hist[256];    // merge: candidates per key bucket
-    uint32_t my[6 * 8 + 2];  // this workgroup's slot payload (R <= 8)
+    uint32_t my[5 * 8 + 2];  // this workgroup's slot payload (R <= 8)
 };
 
 // Per-thread telemetry accumulators.
@@ -197,7 +200,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                              uint32_t &epoch, unsigned char *smem, RoundShared &sh, RoundTele &tl,
                              bool record_trace, bool clocks)
 {
-    constexpr int W = 6 * R + 2;  // words per slot
+    constexpr int W = 5 * R + 2;  // words per slot
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     // the wavefront index is uniform: as a scalar it keeps wave-strided loops
     // and their addressing off the exec mask
@@ -231,8 +234,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
     float *cx = reinterpret_cast<float *>(tlist + ntl);  // [G][R] candidates
     float *cy = cx + G * R;
     float *cz = cy + G * R;
-    float *ctd = cz + G * R;   // true round-start d2; becomes the selection d2 when picked
-    float *cld = ctd + G * R;  // local d2
+    float *cld = cz + G * R;  // local d2 (the selection d2 of a certified candidate)
     uint32_t *corig = reinterpret_cast<uint32_t *>(cld + G * R);
     uint32_t *sidx = corig + G * R;  // merge order; its first P entries are the round's picks
     float *px = reinterpret_cast<float *>(sidx + sort_cap(G, R));
@@ -349,11 +351,11 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 if (s == R || bk == 0) {
                     // the bound (or an empty workgroup): no more local candidates
                     if (lane == 0) {
-                        sh.my[6 * R] = (uint32_t)(bk >> 32);
-                        sh.my[6 * R + 1] = (uint32_t)bk;
+                        sh.my[5 * R] = (uint32_t)(bk >> 32);
+                        sh.my[5 * R + 1] = (uint32_t)bk;
                         for (int q = s; q < R; ++q)
-                            for (int w = 0; w < 6; ++w)
-                                sh.my[6 * q + w] = 0;
+                            for (int w = 0; w < 5; ++w)
+                                sh.my[5 * q + w] = 0;
                     }
                     break;
                 }
@@ -361,12 +363,11 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 const uint32_t p = tbestl[bt];
                 const float lx = px[p], ly = py[p], lz = pz[p];
                 if (lane == 0) {
-                    sh.my[6 * s + 0] = __float_as_uint(lx);
-                    sh.my[6 * s + 1] = __float_as_uint(ly);
-                    sh.my[6 * s + 2] = __float_as_uint(lz);
-                    sh.my[6 * s + 3] = __float_as_uint(pd[p]);
-                    sh.my[6 * s + 4] = po[p];
-                    sh.my[6 * s + 5] = (uint32_t)(bk >> 32);
+                    sh.my[5 * s + 0] = __float_as_uint(lx);
+                    sh.my[5 * s + 1] = __float_as_uint(ly);
+                    sh.my[5 * s + 2] = __float_as_uint(lz);
+                    sh.my[5 * s + 3] = (uint32_t)(bk >> 32);  // local d2
+                    sh.my[5 * s + 4] = po[p];
                 }
                 // local update with l_s (pruned against the local thresholds)
                 for (int lt0 = 0; lt0 < ntl; lt0 += kWave) {
@@ -461,15 +462,15 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     return false;
                 const int e = tid + kBlock * r, g = e / W, w = e % W;
                 const uint32_t v = (uint32_t)xr;
-                if (w < 6 * R) {
-                    // field f of candidate w / 6: x, y, z, true d2, index, local
-                    // d2; the arrays sit in LDS in the order cx, cy, cz, ctd,
-                    // cld, corig, G * R words apart
-                    const int f = w % 6;
-                    reinterpret_cast<uint32_t *>(cx)[(f ^ (f >> 2)) * (G * R) + g * R + w / 6] = v;
+                if (w < 5 * R) {
+                    // field f of candidate w / 5: x, y, z, local d2, index; the
+                    // arrays sit in LDS in that order (cx, cy, cz, cld, corig),
+                    // G * R words apart
+                    const int f = w % 5;
+                    reinterpret_cast<uint32_t *>(cx)[f * (G * R) + g * R + w / 5] = v;
                 } else {
                     // the bound key: high half first (little-endian halves)
-                    reinterpret_cast<uint32_t *>(bkey + g * (R + 1) + R)[w == 6 * R ? 1 : 0] = v;
+                    reinterpret_cast<uint32_t *>(bkey + g * (R + 1) + R)[w == 5 * R ? 1 : 0] = v;
                 }
                 return true;
             };
@@ -569,7 +570,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
 
         // =============== M: certified merge (whole workgroup) ===============
         // Candidates are taken in descending order of local key; each one is
-        // certified when its true distance (the round-start value lowered by
+        // certified when its true distance (its local distance lowered by
         // every earlier pick of the round) still equals its local distance,
         // and the round ends at the first one that is not.  Taking the group
         // with the largest bound B_g at every step visits exactly this order
@@ -736,15 +737,16 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 uint32_t P = from;
                 for (uint32_t base = from; base < lim; base += kWave) {
                     const uint32_t n = min((uint32_t)kWave, lim - base);
-                    // true distance of every position of the chunk: its round-start
+                    // true distance of every position of the chunk: its local
                     // value, lowered by every earlier position (the earlier ones
-                    // are all picks if this one is reached); wave w takes the
-                    // earlier positions q = w mod 4 (broadcast reads)
+                    // are all picks if this one is reached; the group's own ones
+                    // change nothing); wave w takes the earlier positions
+                    // q = w mod 4 (broadcast reads)
                     {
                         const uint32_t e = base + lane;
                         const bool in = (uint32_t)lane < n;
                         const float x = pkx[in ? e : base], y = pky[in ? e : base], z = pkz[in ? e : base];
-                        float t = in ? ctd[ord[e]] : INFINITY;
+                        float t = in ? cld[ord[e]] : INFINITY;
                         const uint32_t qend = base + n - 1;  // no position reaches past it
                         uint32_t q = wave;
                         for (; q + 3 * kWavesPerBlock < qend; q += 4 * kWavesPerBlock) {
@@ -776,8 +778,6 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     }
                     __syncthreads();
                     const uint32_t ok = sh.mfail;
-                    if (tid < (int)ok)
-                        ctd[ord[base + tid]] = __uint_as_float(sh.cmin[tid]);  // the distance at selection
                     if (tid < kWave)
                         sh.cmin[tid] = 0x7f800000u;  // +inf for the next chunk
                     P = base + ok;
@@ -806,7 +806,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     const uint32_t c = ord[k];
                     job.out_idx[j + k] = (int32_t)corig[c];
                     if (job.out_d2)
-                        job.out_d2[j + k] = ctd[c];
+                        job.out_d2[j + k] = cld[c];
                 }
             }
         }
