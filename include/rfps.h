@@ -114,8 +114,8 @@ typedef struct rfps_telemetry {
     int64_t ticks_merge;
     int64_t ticks_apply;
     int64_t tick_hz;        /* rate of those ticks (filled in by the reader) */
-    /* of ticks_exchange, the part spent waiting until every workgroup had
-     * published (the rest is reading the slots) */
+    /* of ticks_exchange, the part spent re-reading slot words that were not
+     * yet published at the first pass (waiting for the slowest workgroup) */
     int64_t ticks_wait;
     int64_t reserved;
 } rfps_telemetry;

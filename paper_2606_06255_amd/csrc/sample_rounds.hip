@@ -415,37 +415,19 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         }
 
         // =============== X: publish and read every slot ===============
+        // Every word carries the round's epoch.  The readers go over all words
+        // of all slots word-major (neighbouring threads, neighbouring words)
+        // until each word shows the epoch, keeping all of a thread's missing
+        // words in flight in every pass: reading the slots that are ready
+        // overlaps waiting for the rest, and words of one slot need not
+        // become visible in the order they were written.
         unsigned long long t_pub = trace ? wall_clock64() : 0ull;
         if (wave == 0) {
             unsigned long long *slot = board + ((size_t)(epoch & 1u) * G + rank) * kMaxSlotWords;
-            for (int w = lane; w < W - 1; w += kWave)
+            for (int w = lane; w < W; w += kWave)
                 bstore<S>(slot + w, ((unsigned long long)epoch << 32) | sh.my[w]);
-            if (lane == 0)
-                bstore<S>(slot + W - 1, ((unsigned long long)epoch << 32) | sh.my[W - 1]);
         }
-        // wait until the last word of every slot carries the epoch (one word
-        // polled per slot), then read all words of all slots word-major, so
-        // that neighbouring threads read neighbouring words; a word counts
-        // once it carries the epoch (each word is checked: words of one slot
-        // need not become visible in the order they were written)
-        if (tid < G) {
-            const unsigned long long *last = board + ((size_t)(epoch & 1u) * G + tid) * kMaxSlotWords + W - 1;
-            uint32_t spin = 0;
-            for (; spin < kSpinLimit; ++spin) {
-                binvalidate<S>();
-                const uint32_t ep = (uint32_t)(bload<S>(last) >> 32);
-                if (ep == epoch)
-                    break;
-                if (ep == kAbortEpoch)
-                    spin = kSpinLimit - 1;
-            }
-            if (spin >= kSpinLimit)
-                sh.abort = 1;
-        }
-        __syncthreads();
-        if (clocks)
-            tl.ph[4] += wall_clock64() - t_mark;
-        if (!sh.abort) {
+        {
             const int total = G * W;
             const unsigned long long *sbase = board + (size_t)(epoch & 1u) * G * kMaxSlotWords;
             unsigned long long pend = 0;
@@ -478,38 +460,22 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 const int e = tid + kBlock * r;
                 return sbase + (size_t)(e / W) * kMaxSlotWords + e % W;
             };
-            // one pass with every load in flight at once (at most 32 per thread)
             constexpr int kFast = W < 32 ? W : 32;
-            binvalidate<S>();
-#pragma unroll
-            for (int r0 = 0; r0 < W; r0 += kFast) {
-                unsigned long long x[kFast];
-#pragma unroll
-                for (int q = 0; q < kFast; ++q) {
-                    const int r = r0 + q;
-                    x[q] = (r < W && ((pend >> r) & 1ull)) ? bload<S>(word(r)) : 0ull;
-                }
-#pragma unroll
-                for (int q = 0; q < kFast; ++q) {
-                    const int r = r0 + q;
-                    if (r < W && ((pend >> r) & 1ull) && take(r, x[q]))
-                        pend &= ~(1ull << r);
-                }
-            }
-            // words not yet visible (rare): poll them in small groups
-            constexpr int kChunk = 8;
+            unsigned long long t_first = 0;
             for (uint32_t spin = 0; pend && !ab && spin < kSpinLimit; ++spin) {
+                if (clocks && spin == 1)
+                    t_first = wall_clock64();  // the passes after the first are waiting
                 binvalidate<S>();
-#pragma unroll 1
-                for (int r0 = 0; r0 < W; r0 += kChunk) {
-                    unsigned long long x[kChunk];
 #pragma unroll
-                    for (int q = 0; q < kChunk; ++q) {
+                for (int r0 = 0; r0 < W; r0 += kFast) {
+                    unsigned long long x[kFast];
+#pragma unroll
+                    for (int q = 0; q < kFast; ++q) {
                         const int r = r0 + q;
                         x[q] = (r < W && ((pend >> r) & 1ull)) ? bload<S>(word(r)) : 0ull;
                     }
 #pragma unroll
-                    for (int q = 0; q < kChunk; ++q) {
+                    for (int q = 0; q < kFast; ++q) {
                         const int r = r0 + q;
                         if (r < W && ((pend >> r) & 1ull) && take(r, x[q]))
                             pend &= ~(1ull << r);
@@ -518,6 +484,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             }
             if (pend)
                 sh.abort = 1;
+            if (clocks && t_first)
+                tl.ph[4] += wall_clock64() - t_first;
         }
         __syncthreads();
         if (!sh.abort) {
@@ -673,55 +641,74 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             // Order by counting: the rank of a candidate within a part of the
             // list is the number of larger keys plus the number of equal keys
             // (repeats of one point) earlier in the part.  Every thread keeps
-            // its candidates' keys in registers and reads the part once.
+            // its candidates' distances in registers and reads the part once,
+            // counting larger and equal distances (the high halves of the
+            // keys); a candidate whose distance occurs more than once in the
+            // part is then ranked again on whole keys.
             uint32_t *ord = reinterpret_cast<uint32_t *>(bkey);  // bkey is not read again this round
-            auto rank_part = [&](auto per_thread, uint32_t lo, uint32_t hi, auto key_at) {
+            auto rank_part = [&](auto per_thread, uint32_t lo, uint32_t hi, auto key_at, auto dist_at) {
                 constexpr int U = decltype(per_thread)::value;
-                unsigned long long mk[U];
-                uint32_t rk[U];
+                uint32_t mh[U], gt[U], eq[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const uint32_t i = lo + tid + kBlock * u;
-                    mk[u] = i < hi ? key_at(i) : 0ull;
-                    rk[u] = 0;
+                    mh[u] = i < hi ? dist_at(i) : 0u;
+                    gt[u] = 0;
+                    eq[u] = 0;
                 }
-                auto count = [&](uint32_t q, unsigned long long kq) {
+                auto count = [&](uint32_t kh) {
 #pragma unroll
-                    for (int u = 0; u < U; ++u)
-                        rk[u] += (kq > mk[u] || (kq == mk[u] && q < lo + tid + kBlock * u)) ? 1u : 0u;
+                    for (int u = 0; u < U; ++u) {
+                        gt[u] += kh > mh[u] ? 1u : 0u;
+                        eq[u] += kh == mh[u] ? 1u : 0u;
+                    }
                 };
                 uint32_t q0 = lo;
                 for (; q0 + 8 <= hi; q0 += 8) {
-                    unsigned long long kq[8];
+                    uint32_t kh[8];
 #pragma unroll
                     for (int v = 0; v < 8; ++v)
-                        kq[v] = key_at(q0 + v);
+                        kh[v] = dist_at(q0 + v);
 #pragma unroll
                     for (int v = 0; v < 8; ++v)
-                        count(q0 + v, kq[v]);
+                        count(kh[v]);
                 }
                 for (; q0 < hi; ++q0)
-                    count(q0, key_at(q0));
+                    count(dist_at(q0));
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const uint32_t i = lo + tid + kBlock * u;
-                    if (i < hi)
-                        ord[lo + rk[u]] = sidx[i];
+                    if (i < hi) {
+                        uint32_t r = gt[u];
+                        if (eq[u] > 1) {
+                            // equal distances: whole keys decide, list position
+                            // among repeats of one point
+                            const unsigned long long mk = key_at(i);
+                            r = 0;
+                            for (uint32_t q = lo; q < hi; ++q) {
+                                const unsigned long long kq = key_at(q);
+                                r += (kq > mk || (kq == mk && q < i)) ? 1u : 0u;
+                            }
+                        }
+                        ord[lo + r] = sidx[i];
+                    }
                 }
             };
-            auto rank_range = [&](uint32_t lo, uint32_t hi, auto key_at) {
+            auto rank_range = [&](uint32_t lo, uint32_t hi, auto key_at, auto dist_at) {
                 const uint32_t n = hi - lo;
                 if (n <= kBlock)
-                    rank_part(std::integral_constant<int, 1>(), lo, hi, key_at);
+                    rank_part(std::integral_constant<int, 1>(), lo, hi, key_at, dist_at);
                 else if (n <= 2 * kBlock)
-                    rank_part(std::integral_constant<int, 2>(), lo, hi, key_at);
+                    rank_part(std::integral_constant<int, 2>(), lo, hi, key_at, dist_at);
                 else if (n <= 4 * kBlock)
-                    rank_part(std::integral_constant<int, 4>(), lo, hi, key_at);
+                    rank_part(std::integral_constant<int, 4>(), lo, hi, key_at, dist_at);
                 else
-                    rank_part(std::integral_constant<int, 8>(), lo, hi, key_at);
+                    rank_part(std::integral_constant<int, 8>(), lo, hi, key_at, dist_at);
                 __syncthreads();
             };
-            rank_range(0, Lf, [&](uint32_t i) { return skey[i]; });
+            rank_range(
+                0, Lf, [&](uint32_t i) { return skey[i]; },
+                [&](uint32_t i) { return reinterpret_cast<const uint32_t *>(skey)[2 * i + 1]; });
             const uint32_t pmax = min(min(L, (uint32_t)kMaxRoundPicks), (uint32_t)(job.m - j));
             // certifies positions [from, lim) of the order; returns the end of
             // the certified prefix
@@ -793,10 +780,13 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 // it (all its keys are smaller) and go on.  The staged pick
                 // coordinates share their words with the stored keys, so these
                 // keys are formed again from the candidates' distances and indices.
-                rank_range(Lf, L, [&](uint32_t i) {
-                    const uint32_t c = sidx[i];
-                    return ((unsigned long long)__float_as_uint(cld[c]) << 32) | (~corig[c]);
-                });
+                rank_range(
+                    Lf, L,
+                    [&](uint32_t i) {
+                        const uint32_t c = sidx[i];
+                        return ((unsigned long long)__float_as_uint(cld[c]) << 32) | (~corig[c]);
+                    },
+                    [&](uint32_t i) { return __float_as_uint(cld[sidx[i]]); });
                 P = certify(P, pmax);
             }
             if (tid == 0)
