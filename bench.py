@@ -38,6 +38,8 @@ WORKLOADS = {
     "room": "indoor room-like cloud, N=80,000, M=20,000",
     "lidar": "spinning LiDAR-like cloud, 64 beams x 1800 azimuth minus 576 drops, N=114,624, M=28,656",
     "cube": "uniform unit cube, N=4096, M=1024",
+    "lidar_stages": "spinning LiDAR-like cloud, N=114,624, FPS in three stages 114,624 -> 28,656 -> 7,164 -> "
+                    "1,791, each stage sampling the previous stage's picks in pick order",
     "batch": "32 uneven clouds in one call, N_i log-uniform in [8000, 120000], even i room-like, odd i "
              "LiDAR-like, M_i = N_i // 4, int32 CSR offsets",
 }
@@ -118,6 +120,10 @@ def main():
 
     if args.workload == "batch":
         result = run_batch(args, rf, dev, stream)
+        print(json.dumps(result), flush=True)
+        return 0
+    if args.workload == "lidar_stages":
+        result = run_stages(args, rf, dev, stream)
         print(json.dumps(result), flush=True)
         return 0
 
@@ -212,7 +218,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "n_points": N,
                    "m": M, "start": 0, "n_vox": n_vox, "tile": 64, "lookahead": args.lookahead or 2,
-                   "groups": args.groups or torch.cuda.get_device_properties(dev).multi_processor_count},
+                   "groups": args.groups or (torch.cuda.get_device_properties(dev).multi_processor_count //
+                                             (1 if N >= 65536 else 2))},
         "ms_per_cloud": ms_per_step,
         "build_ms": build_ms,
         "sample_ms": float(np.mean(sample_ms)),
@@ -225,7 +232,7 @@ def main():
                         "p90": float(np.percentile(ex_us, 90)), "round_p50": float(np.median(it_us)),
                         "note": "publish to merged outcome of workgroup 0, per exchange round"},
         "latency_floor_ms": float(np.median(ex_us)) * len(tr) / 1e3,
-        "roofline": {"bound": "hbm", "kernel": "k_rfps_rounds<4>", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": "k_rfps_rounds<%d>" % (args.lookahead or 2), "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "alg_bytes_per_launch": alg_bytes, "source_digest": digest},
     }
@@ -324,6 +331,118 @@ def cpu_baseline(clouds, ms, gpu_idx, gpu_d2, seconds):
                       "%d cloud%s), plain O(N*M) FPS in C, OpenMP" % (100 * frac, sel, total - len(ms), len(ms),
                                                                       "s" if len(ms) > 1 else ""),
             "seconds": dt, "bitexact_prefix": same}
+
+
+def run_stages(args, rf, dev, stream):
+    """The multi-stage LiDAR workload: one step is all three stages, each an
+    index build and FPS of the previous stage's picks (gathered on the device
+    by rfps_gather_xyz), as a point backbone down-samples."""
+    import numpy as np
+    import torch
+    import synth
+
+    P = synth.lidar(0)
+    sizes = [int(v) for v in synth.lidar_stage_sizes(P.shape[0])]
+    ms = sizes[1:]
+    K = len(ms)
+    xs = [torch.from_numpy(P).to(dev)] + [torch.empty((mm, 3), dtype=torch.float32, device=dev) for mm in ms[:-1]]
+    outs = [(torch.empty(mm, dtype=torch.int32, device=dev), torch.empty(mm, dtype=torch.float32, device=dev))
+            for mm in ms]
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    idxs = [None] * K
+
+    def step(marks=None):
+        for k in range(K):
+            if marks is not None:
+                marks[k][0].record(stream)
+            idxs[k] = rf.build_index(xs[k], reuse=idxs[k])
+            rf.sample(idxs[k], ms[k], 0, lookahead=args.lookahead, out_idx=outs[k][0], out_d2=outs[k][1])
+            if k + 1 < K:
+                rf.gather_xyz(xs[k], outs[k][0], out=xs[k + 1])
+            if marks is not None:
+                marks[k][1].record(stream)
+
+    # ---- timed region ---------------------------------------------------------
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    for k in range(K):
+        st = rf.read_status(idxs[k])
+        if st != 0:
+            raise rf.RfpsError(st, "device status, stage %d" % (k + 1))
+    a, b = ev(), ev()
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    a.record(stream)
+    for _ in range(args.steps):
+        step()
+    b.record(stream)
+    torch.cuda.synchronize()
+    wall1 = time.perf_counter()
+    ms_per_step = a.elapsed_time(b) / args.steps
+    for k in range(K):
+        st = rf.read_status(idxs[k])
+        if st != 0:
+            raise rf.RfpsError(st, "device status, stage %d" % (k + 1))
+    got = [(o[0].cpu().numpy().copy(), o[1].cpu().numpy().copy()) for o in outs]
+    log("timed %d steps: %.3f ms/step (wall %.3f ms/step)" % (args.steps, ms_per_step,
+                                                              1e3 * (wall1 - wall0) / args.steps))
+    # ---- untimed: per-stage times and comparators -----------------------------
+    marks = [(ev(), ev()) for _ in range(K)]
+    step(marks)
+    torch.cuda.synchronize()
+    stage_ms = [m0.elapsed_time(m1) for m0, m1 in marks]
+    pws = rf.PlainWorkspace(P.shape[0], dev)
+    plain = [(torch.empty(mm, dtype=torch.int32, device=dev), torch.empty(mm, dtype=torch.float32, device=dev))
+             for mm in ms]
+    pxs = [xs[0]] + [torch.empty((mm, 3), dtype=torch.float32, device=dev) for mm in ms[:-1]]
+
+    def plain_chain():
+        for k in range(K):
+            rf.fps_plain(pxs[k], ms[k], 0, variant=0, ws=pws, out_idx=plain[k][0], out_d2=plain[k][1], check=False)
+            if k + 1 < K:
+                rf.gather_xyz(pxs[k], plain[k][0], out=pxs[k + 1])
+
+    plain_chain()
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record(stream)
+    plain_chain()
+    b.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = a.elapsed_time(b)
+    same = all(np.array_equal(plain[k][0].cpu().numpy(), got[k][0]) and
+               np.array_equal(plain[k][1].cpu().numpy().view(np.uint32), got[k][1].view(np.uint32)) for k in range(K))
+    total_sel = sum(ms)
+    result = {
+        "metric": METRIC,
+        "value": total_sel / (ms_per_step / 1e3),
+        "unit": "selected pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "lidar_stages", "description": WORKLOADS["lidar_stages"], "sizes": sizes,
+                   "start": 0, "n_vox": "default per stage", "lookahead": args.lookahead or 2},
+        "ms_per_cloud": ms_per_step,
+        "stage_ms": stage_ms,
+        "comparators": {"plain_persistent_chain_ms": plain_ms},
+        "speedup_vs_plain_persistent": plain_ms / ms_per_step,
+        "bitexact_vs_plain": bool(same),
+    }
+    if not args.no_cpu_baseline:
+        clouds, cur = [], P
+        for k in range(K):
+            clouds.append(cur)
+            cur = cur[got[k][0]]
+        result["cpu_baseline"] = cpu_baseline(clouds, ms, [g[0] for g in got], [g[1] for g in got],
+                                              args.cpu_seconds)
+    return result
 
 
 def run_batch(args, rf, dev, stream):

@@ -68,7 +68,8 @@ typedef struct rfps_params {
      * its own voxel-level distance.  0 selects 64 (one wavefront). */
     int32_t tile;
     /* Workgroups of the persistent sampler, 1..256 and at most the number of
-     * compute units (all must be resident at once); 0 = one per compute unit. */
+     * compute units (all must be resident at once); 0 = one per compute unit,
+     * or half of them for the multi-pick sampler on clouds below 65,536 points. */
     int32_t groups;
     /* Lookahead depth of the multi-pick sampler: every workgroup proposes
      * this many local candidates per exchange round; 2, 4 or 8 (0 = 2).
@@ -174,6 +175,19 @@ rfps_status rfps_build_index(const float *xyz, int32_t n, const rfps_params *par
 rfps_status rfps_sample(const rfps_index *index, int32_t m, int32_t start,
                         const rfps_params *params, int32_t *out_idx, float *out_d2,
                         void *stream);
+
+/*
+ * Coordinates of the samples in sample order, out[j] = xyz[idx[j]]: the input
+ * of the next stage when a point backbone down-samples in stages (each stage
+ * is FPS of the previous stage's samples, start 0).
+ *   xyz   device, float32 [n][3] (interleaved x, y, z).
+ *   idx   device, int32 [m], e.g. out_idx of rfps_sample; an index outside
+ *         [0, n) yields NaN coordinates (a later build reports them).
+ *   out   device, float32 [m][3]; must not overlap xyz.
+ * Asynchronous on `stream`; host-checked errors return before any work.
+ */
+rfps_status rfps_gather_xyz(const float *xyz, int32_t n, const int32_t *idx, int32_t m, float *out,
+                            void *stream);
 
 /* Waits for the stream, then returns the device-side status recorded in the
  * index workspace by the last build or sampling call (RFPS_OK if none). */

@@ -91,6 +91,8 @@ def lib() -> ctypes.CDLL:
         L.rfps_fps_plain_workspace_size.restype = sz
         L.rfps_fps_plain.argtypes = [vp, i32, i32, i32, i32, i32, vp, sz, vp, vp, vp]
         L.rfps_fps_plain.restype = ctypes.c_int
+        L.rfps_gather_xyz.argtypes = [vp, i32, vp, i32, vp, vp]
+        L.rfps_gather_xyz.restype = ctypes.c_int
         L.rfps_read_plain_status.argtypes = [vp, sz, vp]
         L.rfps_read_plain_status.restype = ctypes.c_int
         L.rfps_batched_workspace_size.argtypes = [i32, i32, P(rfps_params)]
@@ -294,6 +296,20 @@ def fps_plain(xyz: torch.Tensor, m: int, start: int = 0, variant: int = 0, group
     if check:
         _check(lib().rfps_read_plain_status(ws.ptr, ws.nbytes, _stream(dev)), "device status")
     return out_idx, out_d2
+
+
+def gather_xyz(xyz: torch.Tensor, idx: torch.Tensor, out=None):
+    """rfps_gather_xyz: the coordinates of the samples in sample order (the next
+    stage's input when down-sampling in stages)."""
+    _check_xyz(xyz)
+    if not (idx.is_cuda and idx.dtype == torch.int32 and idx.dim() == 1 and idx.is_contiguous()):
+        raise ValueError("idx must be a contiguous int32 CUDA tensor")
+    m = idx.shape[0]
+    if out is None:
+        out = torch.empty((m, 3), dtype=torch.float32, device=xyz.device)
+    _check(lib().rfps_gather_xyz(xyz.data_ptr(), xyz.shape[0], idx.data_ptr(), m, out.data_ptr(),
+                                 _stream(xyz.device)), "rfps_gather_xyz")
+    return out
 
 
 # ---------------------------------------------------------------------------

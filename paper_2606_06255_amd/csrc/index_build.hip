@@ -386,11 +386,34 @@ __global__ __launch_bounds__(kBlock) void k_tiles(const uint32_t *__restrict__ v
     }
 }
 
+// Coordinates of the picks in pick order: the input of the next stage of a
+// multi-stage down-sampling.  An index outside [0, n) gives NaN coordinates,
+// which the next index build reports as non-finite input.
+__global__ __launch_bounds__(kBlock) void k_gather_xyz(const float *__restrict__ xyz, int n,
+                                                       const int32_t *__restrict__ idx, int m,
+                                                       float *__restrict__ out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m)
+        return;
+    const int32_t i = idx[j];
+    const bool ok = i >= 0 && i < n;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        out[3 * (size_t)j + a] = ok ? xyz[3 * (size_t)i + a] : NAN;
+}
+
 }  // namespace rfps
 
 namespace rfps {
 
 static inline int blocks_for(long long n, int per_block) { return (int)((n + per_block - 1) / per_block); }
+
+hipError_t launch_gather_xyz(const float *xyz, int n, const int32_t *idx, int m, float *out, hipStream_t s)
+{
+    k_gather_xyz<<<blocks_for(m, kBlock), kBlock, 0, s>>>(xyz, n, idx, m, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_scan(const uint32_t *in, uint32_t *out, int n, uint32_t *partials, uint32_t *total,
                        hipStream_t s)
@@ -538,42 +561,73 @@ __global__ void k_batch_setup(IndexHeader *hdr, BatchCtl bc, int n, uint32_t *cl
 
 // Per-cloud bounding boxes; flags non-finite coordinates.  A wavefront whose
 // points all belong to one cloud reduces before its atomics.
+// Bounding box of every cloud.  A wavefront takes a run of kBboxRun
+// consecutive points and keeps the running box of the cloud it is in,
+// flushing it with one atomic per bound when the run moves into the next
+// cloud (clouds are contiguous ranges of the input) and at its end.
+constexpr int kBboxRun = 2048;
+
 __global__ __launch_bounds__(kBlock) void k_bbox_batch(const float *__restrict__ xyz, int n, BatchCtl bc,
                                                        uint32_t *cl_bb, IndexHeader *hdr)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    for (int i0 = blockIdx.x * blockDim.x; i0 < n; i0 += gridDim.x * blockDim.x) {
-        const int i = i0 + threadIdx.x;
-        const bool valid = i < n;
-        float p[3] = {0.0f, 0.0f, 0.0f};
-        int c = 0;
-        bool bad = false;
-        if (valid) {
-            c = cloud_of(bc.offsets, bc.batch, i);
+    const int gw = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int nw = gridDim.x * blockDim.x / kWave;
+    bool bad = false;
+    for (int b = gw * kBboxRun; b < n; b += nw * kBboxRun) {
+        const int e = min(b + kBboxRun, n);
+        // (the last cloud runs to n whatever the offsets say, so that
+        // inconsistent offsets, reported by the setup kernel, stay in bounds)
+        int c = cloud_of(bc.offsets, bc.batch, b);
+        int cend = c + 1 < bc.batch ? bc.offsets[c + 1] : n;
+        float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+        auto flush = [&]() {
+#pragma unroll
             for (int a = 0; a < 3; ++a) {
-                p[a] = xyz[3 * (size_t)i + a];
-                bad |= !isfinite(p[a]);
-            }
-        }
-        if (__any(bad) && lane == 0)
-            set_status(&hdr->build_status, RFPS_ERR_NONFINITE);
-        const int c0 = __builtin_amdgcn_readfirstlane(c);
-        if (__all(!valid || c == c0)) {
-            for (int a = 0; a < 3; ++a) {
-                const float lo = wave_min_f32(valid ? p[a] : INFINITY);
-                const float hi = wave_max_f32(valid ? p[a] : -INFINITY);
+                const float lo = wave_min_f32(mn[a]);
+                const float hi = wave_max_f32(mx[a]);
                 if (lane == 0 && lo <= hi) {
-                    atomicMin(&cl_bb[6 * c0 + a], f2ord(lo));
-                    atomicMax(&cl_bb[6 * c0 + 3 + a], f2ord(hi));
+                    atomicMin(&cl_bb[6 * c + a], f2ord(lo));
+                    atomicMax(&cl_bb[6 * c + 3 + a], f2ord(hi));
+                }
+                mn[a] = INFINITY;
+                mx[a] = -INFINITY;
+            }
+        };
+        for (int i0 = b; i0 < e; i0 += kWave) {
+            const int i = i0 + lane;
+            const bool valid = i < e;
+            float p[3] = {0.0f, 0.0f, 0.0f};
+            if (valid) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    p[a] = xyz[3 * (size_t)i + a];
+                    bad |= !isfinite(p[a]);
                 }
             }
-        } else if (valid) {
-            for (int a = 0; a < 3; ++a) {
-                atomicMin(&cl_bb[6 * c + a], f2ord(p[a]));
-                atomicMax(&cl_bb[6 * c + 3 + a], f2ord(p[a]));
+            // the lanes of one step may belong to several clouds
+            bool todo = valid;
+            while (__any(todo)) {
+                const bool mine = todo && i < cend;
+                if (mine) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        mn[a] = fminf(mn[a], p[a]);
+                        mx[a] = fmaxf(mx[a], p[a]);
+                    }
+                }
+                todo = todo && !mine;
+                if (__any(todo)) {
+                    flush();
+                    ++c;
+                    cend = c + 1 < bc.batch ? bc.offsets[c + 1] : n;
+                }
             }
         }
+        flush();
     }
+    if (__any(bad) && lane == 0)
+        set_status(&hdr->build_status, RFPS_ERR_NONFINITE);
 }
 
 // Grid of every cloud: its own box and bins (eq. voxel_size).
@@ -657,7 +711,8 @@ hipError_t launch_build_batch(const IndexView &v, const float *xyz, hipStream_t 
     const int n = v.n, B = v.bc.batch;
     k_batch_reset<<<32, kBlock, 0, s>>>(v.hdr, v.bc, v.cl_bb, v.bstate, v.board);
     k_batch_setup<<<1, kBlock, 0, s>>>(v.hdr, v.bc, n, v.cl_nvox, v.cl_base);
-    k_bbox_batch<<<std::min(blocks_for(n, kBlock), 1024), kBlock, 0, s>>>(xyz, n, v.bc, v.cl_bb, v.hdr);
+    k_bbox_batch<<<std::min(blocks_for(n, kBboxRun * kWavesPerBlock), 1024), kBlock, 0, s>>>(xyz, n, v.bc, v.cl_bb,
+                                                                                          v.hdr);
     k_grid_batch<<<blocks_for(B, kBlock), kBlock, 0, s>>>(v.hdr, v.bc, v.cl_bb, v.cl_nvox, v.cl_pmin, v.cl_L);
     k_voxel_key_batch<<<blocks_for(n, kBlock), kBlock, 0, s>>>(xyz, n, v.bc, v.cl_nvox, v.cl_base, v.cl_pmin,
                                                                v.cl_L, v.cl_bb, v.keyA, v.valA);

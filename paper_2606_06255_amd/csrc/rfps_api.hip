@@ -334,8 +334,14 @@ rfps_status rfps_sample(const rfps_index *index, int32_t m, int32_t start, const
     if (!d->ok)
         return RFPS_ERR_UNSUPPORTED;
     SampleLaunch L;
-    L.G = (params && params->groups) ? params->groups : std::min(d->cus, kMaxGroups);
     L.flags = params ? params->flags : 0u;
+    // default workgroups: every compute unit; clouds below 64k points take
+    // half of them for the multi-pick sampler (a round then exchanges and
+    // merges half the candidates, and each workgroup still owns a few hundred
+    // points: measured 5-10 % faster on 4k-30k point clouds)
+    const int all = std::min(d->cus, kMaxGroups);
+    const bool small = index->n < (1 << 16) && !(L.flags & (RFPS_F_SINGLE_PICK | RFPS_F_NO_PRUNE));
+    L.G = (params && params->groups) ? params->groups : (small ? std::max(1, all / 2) : all);
     // the multi-pick sampler is the default; plain (unpruned) sampling and an
     // explicit request use one selection per exchange
     const bool single = (L.flags & (RFPS_F_SINGLE_PICK | RFPS_F_NO_PRUNE)) != 0;
@@ -424,6 +430,20 @@ int32_t rfps_read_trace(const rfps_index *index, void *stream, uint64_t *out, in
     if (ticks_per_s)
         *ticks_per_s = d->wall_hz;
     return cnt;
+}
+
+rfps_status rfps_gather_xyz(const float *xyz, int32_t n, const int32_t *idx, int32_t m, float *out, void *stream)
+{
+    if (!xyz || !idx || !out || n < 1 || n > kMaxPoints || m < 1 || m > kMaxPoints)
+        return RFPS_ERR_INVALID_ARG;
+    const DeviceInfo *d = device_info();
+    if (!d)
+        return RFPS_ERR_DEVICE;
+    if (!d->ok)
+        return RFPS_ERR_UNSUPPORTED;
+    return launch_gather_xyz(xyz, n, idx, m, out, static_cast<hipStream_t>(stream)) == hipSuccess
+               ? RFPS_OK
+               : RFPS_ERR_DEVICE;
 }
 
 size_t rfps_fps_plain_workspace_size(int32_t n, int32_t variant)

@@ -116,6 +116,9 @@ static int run_batch(int argc, char **argv)
 
 int main(int argc, char **argv)
 {
+    // line-buffered, so that the result lines are written even when a
+    // profiler attached to the process fails while the process exits
+    setvbuf(stdout, nullptr, _IOLBF, 0);
     if (argc > 1 && strcmp(argv[1], "--batch") == 0)
         return run_batch(argc, argv);
     if (argc < 3) {

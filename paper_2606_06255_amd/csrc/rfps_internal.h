@@ -377,6 +377,7 @@ __device__ __forceinline__ void publish_abort(unsigned long long *board, int G, 
 // `s` and return the first launch error.
 // ---------------------------------------------------------------------------
 hipError_t launch_build_index(const IndexView &v, const float *xyz, hipStream_t s);
+hipError_t launch_gather_xyz(const float *xyz, int n, const int32_t *idx, int m, float *out, hipStream_t s);
 hipError_t launch_scan(const uint32_t *in, uint32_t *out, int n, uint32_t *partials, uint32_t *total,
                        hipStream_t s);
 

@@ -27,7 +27,8 @@ def L():
 
 def test_every_declared_symbol_is_exported(L):
     names = declared_functions()
-    assert len(names) >= 27 and "rfps_mlp_train_step" in names and "rfps_sample_batched" in names
+    assert len(names) >= 28
+    assert "rfps_gather_xyz" in names and "rfps_mlp_train_step" in names and "rfps_sample_batched" in names
     for name in names:
         assert hasattr(L, name), name
 
@@ -106,6 +107,12 @@ def test_invalid_arguments_return_before_device_work(L):
     assert L.rfps_fps_plain(fake, 10, 5, 0, 0, 0, None, 1 << 30, out, None, None) == 3
     assert L.rfps_fps_plain(fake, 10, 5, 0, 0, 0, fake, 16, out, None, None) == 3
     assert L.rfps_read_plain_status(None, 0, None) == 3
+    # stage gather: NULL pointers and sizes
+    assert L.rfps_gather_xyz(None, 10, fake, 5, out, None) == 1
+    assert L.rfps_gather_xyz(fake, 10, None, 5, out, None) == 1
+    assert L.rfps_gather_xyz(fake, 10, fake, 5, None, None) == 1
+    assert L.rfps_gather_xyz(fake, 0, fake, 5, out, None) == 1
+    assert L.rfps_gather_xyz(fake, 10, fake, 0, out, None) == 1
     # readers reject bad handles without touching the device
     t = rf.rfps_telemetry()
     assert L.rfps_read_telemetry(None, None, ctypes.byref(t)) == 1

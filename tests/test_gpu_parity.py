@@ -133,15 +133,31 @@ def test_range_shells(oracle_lib):
 
 
 def test_lidar_multistage(oracle_lib):
+    # every stage samples the previous stage's picks in pick order; on the
+    # device the next input comes from rfps_gather_xyz
     m = rf()
     P = synth.lidar(0)
     sizes = synth.lidar_stage_sizes(P.shape[0])
-    cur = P
+    cur, x = P, dev(P)
     for k, mm in enumerate(sizes[1:]):
         ref = oracle_lib.fps(cur, mm, 0, threads=0)
-        got = m.fps(dev(cur), mm, 0)
+        got = m.fps(x, mm, 0)
         assert_same(got, ref, "stage %d" % (k + 1))
         cur = cur[ref[0]]
+        x = m.gather_xyz(x, got[0])
+        assert np.array_equal(host(x).view(np.uint32), cur.view(np.uint32))
+
+
+def test_gather_out_of_range():
+    m = rf()
+    P = synth.cube(4)[:100]
+    idx = torch.tensor([5, -1, 99, 100, 0], dtype=torch.int32, device="cuda:0")
+    got = host(m.gather_xyz(dev(P), idx))
+    assert np.array_equal(got[[0, 2, 4]], P[[5, 99, 0]])
+    assert np.all(np.isnan(got[[1, 3]]))
+    # NaN input is then reported by the next build
+    idx2 = m.build_index(dev(np.ascontiguousarray(got)))
+    assert m.read_status(idx2) == 2
 
 
 def test_edge_cases(oracle_lib):
