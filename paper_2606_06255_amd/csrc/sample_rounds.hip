@@ -169,7 +169,7 @@ struct RoundShared {
     uint32_t redi[kWavesPerBlock];
     uint32_t scan[kWavesPerBlock];
     unsigned long long red2[kWavesPerBlock];
-    uint32_t abort, list_n, npick, mcount, mback, mfail, mtotal, msel;
+    uint32_t abort, list_n, npick, mcount, mfail, mtotal, msel;
     uint32_t cmin[kWave];  // merge: true distances of one chunk of 64 positions (float bits)
     uint32_t hist[256];    // merge: candidates per key bucket
     uint32_t my[5 * 8 + 2];  // this workgroup's slot payload (R <= 8)
@@ -513,10 +513,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 sh.red[wave] = sk;
                 sh.red2[wave] = hk;
             }
-            if (tid == 0) {
+            if (tid == 0)
                 sh.mcount = 0;
-                sh.mback = 0;
-            }
             sh.hist[tid] = 0;
         }
         __syncthreads();
@@ -563,73 +561,19 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 k = c < G * R ? bkey[g * (R + 1) + c % R] : 0ull;
                 return c < G * R && (k > smax || (k == smax && bkey[g * (R + 1) + R] == smax));
             };
-            // Only the first few positions of the order are usually needed:
-            // a histogram of the keys' high halves (distance bits, between S*
-            // and the largest key) finds a bucket above which at least
-            // kSelect candidates lie; those come first in the list and are put
-            // in order alone, the rest only if the round gets that far.
-            constexpr uint32_t kSelect = 128;
-            const uint32_t hlo = (uint32_t)(smax >> 32);
-            const uint32_t span = (uint32_t)(hmax >> 32) - hlo;
-            const int bits = span ? 32 - __clz((int)span) : 0;
-            const int bshift = bits > 8 ? bits - 8 : 0;
-            auto bucket = [&](unsigned long long k) { return ((uint32_t)(k >> 32) - hlo) >> bshift; };
-            for (int c0 = 0; c0 < G * R; c0 += kBlock) {
-                unsigned long long k;
-                if (taken(c0 + tid, k))
-                    atomicAdd(&sh.hist[bucket(k)], 1u);
-            }
-            __syncthreads();
-            if (wave == 0) {
-                uint32_t c4 = 0;
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    c4 += sh.hist[4 * lane + b];
-                uint32_t suf = c4;  // candidates in the buckets of lanes >= this one
-#pragma unroll
-                for (int off = 1; off < kWave; off <<= 1) {
-                    const uint32_t o = (uint32_t)__shfl_down((int)suf, off, kWave);
-                    suf += lane + off < kWave ? o : 0u;
-                }
-                const uint32_t total = (uint32_t)__shfl((int)suf, 0, kWave);
-                const unsigned long long enough = __ballot(suf >= kSelect);
-                const int lt = enough ? 63 - __clzll((long long)enough) : -1;
-                if (lane == 0) {
-                    sh.mtotal = total;
-                    sh.msel = 0;  // everything
-                }
-                if (total > kSelect && lane == lt) {
-                    uint32_t acc = suf - c4;
-                    for (int b = 3; b >= 0; --b) {
-                        acc += sh.hist[4 * lane + b];
-                        if (acc >= kSelect) {
-                            sh.msel = (uint32_t)(4 * lane + b);
-                            break;
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-            const uint32_t L = sh.mtotal, bsel = sh.msel;
+            // the candidates above S*, in any order
             for (int c0 = 0; c0 < G * R; c0 += kBlock) {
                 const int c = c0 + tid;
                 unsigned long long k;
                 const bool keep = taken(c, k);
-                const bool front = keep && bucket(k) >= bsel;
-                const unsigned long long fm = __ballot(front), bm = __ballot(keep && !front);
-                uint32_t fbase = 0, bbase = 0;
-                if (lane == 0) {
-                    if (fm)
-                        fbase = atomicAdd(&sh.mcount, (uint32_t)__popcll(fm));
-                    if (bm)
-                        bbase = atomicAdd(&sh.mback, (uint32_t)__popcll(bm));
-                }
-                fbase = (uint32_t)__shfl((int)fbase, 0, kWave);
-                bbase = (uint32_t)__shfl((int)bbase, 0, kWave);
+                const unsigned long long km = __ballot(keep);
+                uint32_t base = 0;
+                if (lane == 0 && km)
+                    base = atomicAdd(&sh.mcount, (uint32_t)__popcll(km));
+                base = (uint32_t)__shfl((int)base, 0, kWave);
                 const unsigned long long below = lane ? (~0ull >> (kWave - lane)) : 0ull;
                 if (keep) {
-                    const uint32_t pos = front ? fbase + (uint32_t)__popcll(fm & below)
-                                               : L - 1 - (bbase + (uint32_t)__popcll(bm & below));
+                    const uint32_t pos = base + (uint32_t)__popcll(km & below);
                     skey[pos] = k;
                     sidx[pos] = (uint32_t)c;
                 }
@@ -637,22 +581,72 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             if (tid < kWave)
                 sh.cmin[tid] = 0x7f800000u;  // +inf: the chunk minima start here
             __syncthreads();
-            const uint32_t Lf = sh.mcount;  // the front part: keys above every key behind it
-            // Order by counting: the rank of a candidate within a part of the
-            // list is the number of larger keys plus the number of equal keys
-            // (repeats of one point) earlier in the part.  Every thread keeps
-            // its candidates' distances in registers and reads the part once,
-            // counting larger and equal distances (the high halves of the
-            // keys); a candidate whose distance occurs more than once in the
-            // part is then ranked again on whole keys.
+            const uint32_t L = sh.mcount;
+            // Only the first positions of the order are usually needed.  With
+            // more than kSelect candidates, a histogram of the keys' high halves
+            // (distance bits, between S* and the largest key) finds the bucket
+            // above which at least kSelect of them lie; those keys (>= kthr),
+            // the front, are put in order and certified first, the rest only if
+            // the round gets that far.
+            constexpr uint32_t kSelect = 128;
+            unsigned long long kthr = 0;
+            uint32_t Lf = L;
+            if (L > kSelect) {
+                const uint32_t hlo = (uint32_t)(smax >> 32);
+                const uint32_t span = (uint32_t)(hmax >> 32) - hlo;
+                const int bits = span ? 32 - __clz((int)span) : 0;
+                const int bshift = bits > 8 ? bits - 8 : 0;
+                for (uint32_t q = tid; q < L; q += kBlock)
+                    atomicAdd(&sh.hist[((uint32_t)(skey[q] >> 32) - hlo) >> bshift], 1u);
+                __syncthreads();
+                if (wave == 0) {
+                    uint32_t c4 = 0;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        c4 += sh.hist[4 * lane + b];
+                    uint32_t suf = c4;  // candidates in the buckets of lanes >= this one
+#pragma unroll
+                    for (int off = 1; off < kWave; off <<= 1) {
+                        const uint32_t o = (uint32_t)__shfl_down((int)suf, off, kWave);
+                        suf += lane + off < kWave ? o : 0u;
+                    }
+                    // the last lane whose suffix holds kSelect (lane 0's holds L)
+                    const unsigned long long enough = __ballot(suf >= kSelect);
+                    const int lt = 63 - __clzll((long long)enough);
+                    if (lane == lt) {
+                        uint32_t acc = suf - c4;
+                        for (int b = 3; b >= 0; --b) {
+                            acc += sh.hist[4 * lane + b];
+                            if (acc >= kSelect) {
+                                sh.msel = (uint32_t)(4 * lane + b);
+                                sh.mtotal = acc;
+                                break;
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+                kthr = (unsigned long long)(hlo + (sh.msel << bshift)) << 32;
+                Lf = sh.mtotal;
+            }
+            // Order by counting: the rank of a candidate is the number of larger
+            // keys in the list plus the number of equal keys (repeats of one
+            // point) earlier in the list.  Every thread keeps its candidates'
+            // distances in registers and reads the list once, counting larger
+            // and equal distances (the high halves of the keys); a candidate
+            // whose distance occurs more than once is then ranked again on
+            // whole keys.  Front and rest get their ranks in separate calls
+            // (all keys of the front exceed all others).
             uint32_t *ord = reinterpret_cast<uint32_t *>(bkey);  // bkey is not read again this round
-            auto rank_part = [&](auto per_thread, uint32_t lo, uint32_t hi, auto key_at, auto dist_at) {
+            auto rank_part = [&](auto per_thread, bool front, auto key_at, auto dist_at) {
                 constexpr int U = decltype(per_thread)::value;
                 uint32_t mh[U], gt[U], eq[U];
+                bool mine[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const uint32_t i = lo + tid + kBlock * u;
-                    mh[u] = i < hi ? dist_at(i) : 0u;
+                    const uint32_t i = tid + kBlock * u;
+                    mine[u] = i < L && ((key_at(i) >= kthr) == front);
+                    mh[u] = i < L ? dist_at(i) : 0u;
                     gt[u] = 0;
                     eq[u] = 0;
                 }
@@ -663,8 +657,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                         eq[u] += kh == mh[u] ? 1u : 0u;
                     }
                 };
-                uint32_t q0 = lo;
-                for (; q0 + 8 <= hi; q0 += 8) {
+                uint32_t q0 = 0;
+                for (; q0 + 8 <= L; q0 += 8) {
                     uint32_t kh[8];
 #pragma unroll
                     for (int v = 0; v < 8; ++v)
@@ -673,41 +667,40 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     for (int v = 0; v < 8; ++v)
                         count(kh[v]);
                 }
-                for (; q0 < hi; ++q0)
+                for (; q0 < L; ++q0)
                     count(dist_at(q0));
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const uint32_t i = lo + tid + kBlock * u;
-                    if (i < hi) {
+                    const uint32_t i = tid + kBlock * u;
+                    if (mine[u]) {
                         uint32_t r = gt[u];
                         if (eq[u] > 1) {
                             // equal distances: whole keys decide, list position
                             // among repeats of one point
                             const unsigned long long mk = key_at(i);
                             r = 0;
-                            for (uint32_t q = lo; q < hi; ++q) {
+                            for (uint32_t q = 0; q < L; ++q) {
                                 const unsigned long long kq = key_at(q);
                                 r += (kq > mk || (kq == mk && q < i)) ? 1u : 0u;
                             }
                         }
-                        ord[lo + r] = sidx[i];
+                        ord[r] = sidx[i];
                     }
                 }
             };
-            auto rank_range = [&](uint32_t lo, uint32_t hi, auto key_at, auto dist_at) {
-                const uint32_t n = hi - lo;
-                if (n <= kBlock)
-                    rank_part(std::integral_constant<int, 1>(), lo, hi, key_at, dist_at);
-                else if (n <= 2 * kBlock)
-                    rank_part(std::integral_constant<int, 2>(), lo, hi, key_at, dist_at);
-                else if (n <= 4 * kBlock)
-                    rank_part(std::integral_constant<int, 4>(), lo, hi, key_at, dist_at);
+            auto order_part = [&](bool front, auto key_at, auto dist_at) {
+                if (L <= kBlock)
+                    rank_part(std::integral_constant<int, 1>(), front, key_at, dist_at);
+                else if (L <= 2 * kBlock)
+                    rank_part(std::integral_constant<int, 2>(), front, key_at, dist_at);
+                else if (L <= 4 * kBlock)
+                    rank_part(std::integral_constant<int, 4>(), front, key_at, dist_at);
                 else
-                    rank_part(std::integral_constant<int, 8>(), lo, hi, key_at, dist_at);
+                    rank_part(std::integral_constant<int, 8>(), front, key_at, dist_at);
                 __syncthreads();
             };
-            rank_range(
-                0, Lf, [&](uint32_t i) { return skey[i]; },
+            order_part(
+                true, [&](uint32_t i) { return skey[i]; },
                 [&](uint32_t i) { return reinterpret_cast<const uint32_t *>(skey)[2 * i + 1]; });
             const uint32_t pmax = min(min(L, (uint32_t)kMaxRoundPicks), (uint32_t)(job.m - j));
             // certifies positions [from, lim) of the order; returns the end of
@@ -780,8 +773,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 // it (all its keys are smaller) and go on.  The staged pick
                 // coordinates share their words with the stored keys, so these
                 // keys are formed again from the candidates' distances and indices.
-                rank_range(
-                    Lf, L,
+                order_part(
+                    false,
                     [&](uint32_t i) {
                         const uint32_t c = sidx[i];
                         return ((unsigned long long)__float_as_uint(cld[c]) << 32) | (~corig[c]);
