@@ -169,7 +169,7 @@ struct RoundShared {
     uint32_t redi[kWavesPerBlock];
     uint32_t scan[kWavesPerBlock];
     unsigned long long red2[kWavesPerBlock];
-    uint32_t abort, list_n, npick, mcount, mfail, mtotal, msel;
+    uint32_t abort, list_n, npick, mcount, pfront, pback, mfail, mtotal, msel;
     uint32_t cmin[kWave];  // merge: true distances of one chunk of 64 positions (float bits)
     uint32_t hist[256];    // merge: candidates per key bucket
     uint32_t my[5 * 8 + 2];  // this workgroup's slot payload (R <= 8)
@@ -513,8 +513,11 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 sh.red[wave] = sk;
                 sh.red2[wave] = hk;
             }
-            if (tid == 0)
+            if (tid == 0) {
                 sh.mcount = 0;
+                sh.pfront = 0;
+                sh.pback = 0;
+            }
             sh.hist[tid] = 0;
         }
         __syncthreads();
@@ -561,7 +564,19 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 k = c < G * R ? bkey[g * (R + 1) + c % R] : 0ull;
                 return c < G * R && (k > smax || (k == smax && bkey[g * (R + 1) + R] == smax));
             };
-            // the candidates above S*, in any order
+            // Only the first positions of the order are usually needed.  The
+            // candidates above S* are compacted (in any order) while a
+            // histogram of their keys' high halves (distance bits, between S*
+            // and the largest key) is counted; with more than kSelect of them,
+            // the bucket above which at least kSelect lie splits the list into
+            // a front (keys >= kthr) that is put in order and certified first,
+            // and the rest, ordered only if the round gets that far.
+            constexpr uint32_t kSelect = 128;
+            const uint32_t hlo = (uint32_t)(smax >> 32);
+            const uint32_t span = (uint32_t)(hmax >> 32) - hlo;
+            const int bits = span ? 32 - __clz((int)span) : 0;
+            const int bshift = bits > 8 ? bits - 8 : 0;
+            const unsigned long long below = lane ? (~0ull >> (kWave - lane)) : 0ull;
             for (int c0 = 0; c0 < G * R; c0 += kBlock) {
                 const int c = c0 + tid;
                 unsigned long long k;
@@ -571,34 +586,19 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 if (lane == 0 && km)
                     base = atomicAdd(&sh.mcount, (uint32_t)__popcll(km));
                 base = (uint32_t)__shfl((int)base, 0, kWave);
-                const unsigned long long below = lane ? (~0ull >> (kWave - lane)) : 0ull;
                 if (keep) {
                     const uint32_t pos = base + (uint32_t)__popcll(km & below);
                     skey[pos] = k;
                     sidx[pos] = (uint32_t)c;
+                    atomicAdd(&sh.hist[((uint32_t)(k >> 32) - hlo) >> bshift], 1u);
                 }
             }
             if (tid < kWave)
                 sh.cmin[tid] = 0x7f800000u;  // +inf: the chunk minima start here
             __syncthreads();
             const uint32_t L = sh.mcount;
-            // Only the first positions of the order are usually needed.  With
-            // more than kSelect candidates, a histogram of the keys' high halves
-            // (distance bits, between S* and the largest key) finds the bucket
-            // above which at least kSelect of them lie; those keys (>= kthr),
-            // the front, are put in order and certified first, the rest only if
-            // the round gets that far.
-            constexpr uint32_t kSelect = 128;
-            unsigned long long kthr = 0;
             uint32_t Lf = L;
             if (L > kSelect) {
-                const uint32_t hlo = (uint32_t)(smax >> 32);
-                const uint32_t span = (uint32_t)(hmax >> 32) - hlo;
-                const int bits = span ? 32 - __clz((int)span) : 0;
-                const int bshift = bits > 8 ? bits - 8 : 0;
-                for (uint32_t q = tid; q < L; q += kBlock)
-                    atomicAdd(&sh.hist[((uint32_t)(skey[q] >> 32) - hlo) >> bshift], 1u);
-                __syncthreads();
                 if (wave == 0) {
                     uint32_t c4 = 0;
 #pragma unroll
@@ -626,27 +626,60 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     }
                 }
                 __syncthreads();
-                kthr = (unsigned long long)(hlo + (sh.msel << bshift)) << 32;
                 Lf = sh.mtotal;
+                // partition: the front to [0, Lf), the rest behind it (the
+                // order inside either part is irrelevant: only repeats of one
+                // point have equal keys)
+                const uint32_t bsel = sh.msel;
+                constexpr int kParts = (kMaxGroups * R + kBlock - 1) / kBlock;  // L <= G * R
+                unsigned long long pk_[kParts];
+                uint32_t pc_[kParts], pp_[kParts];
+#pragma unroll
+                for (int u = 0; u < kParts; ++u) {
+                    const uint32_t i = tid + kBlock * u;
+                    const bool in = i < L;
+                    pk_[u] = in ? skey[i] : 0ull;
+                    pc_[u] = in ? sidx[i] : 0u;
+                    const bool front = in && (((uint32_t)(pk_[u] >> 32) - hlo) >> bshift) >= bsel;
+                    const unsigned long long fm = __ballot(front), bm = __ballot(in && !front);
+                    uint32_t fb = 0, bb = 0;
+                    if (lane == 0) {
+                        if (fm)
+                            fb = atomicAdd(&sh.pfront, (uint32_t)__popcll(fm));
+                        if (bm)
+                            bb = atomicAdd(&sh.pback, (uint32_t)__popcll(bm));
+                    }
+                    fb = (uint32_t)__shfl((int)fb, 0, kWave);
+                    bb = (uint32_t)__shfl((int)bb, 0, kWave);
+                    pp_[u] = !in ? 0xffffffffu
+                                 : (front ? fb + (uint32_t)__popcll(fm & below)
+                                          : Lf + bb + (uint32_t)__popcll(bm & below));
+                }
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < kParts; ++u) {
+                    if (pp_[u] != 0xffffffffu) {
+                        skey[pp_[u]] = pk_[u];
+                        sidx[pp_[u]] = pc_[u];
+                    }
+                }
+                __syncthreads();
             }
-            // Order by counting: the rank of a candidate is the number of larger
-            // keys in the list plus the number of equal keys (repeats of one
-            // point) earlier in the list.  Every thread keeps its candidates'
-            // distances in registers and reads the list once, counting larger
-            // and equal distances (the high halves of the keys); a candidate
-            // whose distance occurs more than once is then ranked again on
-            // whole keys.  Front and rest get their ranks in separate calls
-            // (all keys of the front exceed all others).
+            // Order by counting: the rank of a candidate within a part of the
+            // list is the number of larger keys plus the number of equal keys
+            // (repeats of one point) earlier in the part.  Every thread keeps
+            // its candidates' distances in registers and reads the part once,
+            // counting larger and equal distances (the high halves of the
+            // keys); a candidate whose distance occurs more than once in the
+            // part is then ranked again on whole keys.
             uint32_t *ord = reinterpret_cast<uint32_t *>(bkey);  // bkey is not read again this round
-            auto rank_part = [&](auto per_thread, bool front, auto key_at, auto dist_at) {
+            auto rank_part = [&](auto per_thread, uint32_t lo, uint32_t hi, auto key_at, auto dist_at) {
                 constexpr int U = decltype(per_thread)::value;
                 uint32_t mh[U], gt[U], eq[U];
-                bool mine[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const uint32_t i = tid + kBlock * u;
-                    mine[u] = i < L && ((key_at(i) >= kthr) == front);
-                    mh[u] = i < L ? dist_at(i) : 0u;
+                    const uint32_t i = lo + tid + kBlock * u;
+                    mh[u] = i < hi ? dist_at(i) : 0u;
                     gt[u] = 0;
                     eq[u] = 0;
                 }
@@ -657,8 +690,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                         eq[u] += kh == mh[u] ? 1u : 0u;
                     }
                 };
-                uint32_t q0 = 0;
-                for (; q0 + 8 <= L; q0 += 8) {
+                uint32_t q0 = lo;
+                for (; q0 + 8 <= hi; q0 += 8) {
                     uint32_t kh[8];
 #pragma unroll
                     for (int v = 0; v < 8; ++v)
@@ -667,40 +700,41 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     for (int v = 0; v < 8; ++v)
                         count(kh[v]);
                 }
-                for (; q0 < L; ++q0)
+                for (; q0 < hi; ++q0)
                     count(dist_at(q0));
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const uint32_t i = tid + kBlock * u;
-                    if (mine[u]) {
+                    const uint32_t i = lo + tid + kBlock * u;
+                    if (i < hi) {
                         uint32_t r = gt[u];
                         if (eq[u] > 1) {
                             // equal distances: whole keys decide, list position
                             // among repeats of one point
                             const unsigned long long mk = key_at(i);
                             r = 0;
-                            for (uint32_t q = 0; q < L; ++q) {
+                            for (uint32_t q = lo; q < hi; ++q) {
                                 const unsigned long long kq = key_at(q);
                                 r += (kq > mk || (kq == mk && q < i)) ? 1u : 0u;
                             }
                         }
-                        ord[r] = sidx[i];
+                        ord[lo + r] = sidx[i];
                     }
                 }
             };
-            auto order_part = [&](bool front, auto key_at, auto dist_at) {
-                if (L <= kBlock)
-                    rank_part(std::integral_constant<int, 1>(), front, key_at, dist_at);
-                else if (L <= 2 * kBlock)
-                    rank_part(std::integral_constant<int, 2>(), front, key_at, dist_at);
-                else if (L <= 4 * kBlock)
-                    rank_part(std::integral_constant<int, 4>(), front, key_at, dist_at);
+            auto rank_range = [&](uint32_t lo, uint32_t hi, auto key_at, auto dist_at) {
+                const uint32_t n = hi - lo;
+                if (n <= kBlock)
+                    rank_part(std::integral_constant<int, 1>(), lo, hi, key_at, dist_at);
+                else if (n <= 2 * kBlock)
+                    rank_part(std::integral_constant<int, 2>(), lo, hi, key_at, dist_at);
+                else if (n <= 4 * kBlock)
+                    rank_part(std::integral_constant<int, 4>(), lo, hi, key_at, dist_at);
                 else
-                    rank_part(std::integral_constant<int, 8>(), front, key_at, dist_at);
+                    rank_part(std::integral_constant<int, 8>(), lo, hi, key_at, dist_at);
                 __syncthreads();
             };
-            order_part(
-                true, [&](uint32_t i) { return skey[i]; },
+            rank_range(
+                0, Lf, [&](uint32_t i) { return skey[i]; },
                 [&](uint32_t i) { return reinterpret_cast<const uint32_t *>(skey)[2 * i + 1]; });
             const uint32_t pmax = min(min(L, (uint32_t)kMaxRoundPicks), (uint32_t)(job.m - j));
             // certifies positions [from, lim) of the order; returns the end of
@@ -773,8 +807,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 // it (all its keys are smaller) and go on.  The staged pick
                 // coordinates share their words with the stored keys, so these
                 // keys are formed again from the candidates' distances and indices.
-                order_part(
-                    false,
+                rank_range(
+                    Lf, L,
                     [&](uint32_t i) {
                         const uint32_t c = sidx[i];
                         return ((unsigned long long)__float_as_uint(cld[c]) << 32) | (~corig[c]);
