@@ -70,6 +70,9 @@ struct RoundArgs {
 // Selections one round may settle (the merge stops there; a shorter round is
 // always valid).
 constexpr int kMaxRoundPicks = 512;
+// Failed candidates a round re-lists before it ends (each failure lowers a
+// listed key, so the loop ends anyway; this caps the work of one round).
+constexpr uint32_t kMaxFailures = 64;
 
 // Entries of the merge's sort buffers: the next power of two of G * R, at
 // least 128 (the smallest network the merge runs).
@@ -91,7 +94,7 @@ __host__ __device__ __forceinline__ uint32_t merge_words(uint32_t G, uint32_t R)
 
 __host__ __device__ __forceinline__ uint32_t rounds_lds_need(uint32_t tiles, uint32_t pts, uint32_t G, uint32_t R)
 {
-    return tiles * 60u + pts * 24u + G * R * 20u + G * (R + 1u) * 8u + sort_cap(G, R) * 4u + merge_words(G, R) * 4u +
+    return tiles * 60u + pts * 24u + G * R * 24u + G * (R + 1u) * 8u + sort_cap(G, R) * 4u + merge_words(G, R) * 4u +
            128u;
 }
 
@@ -169,10 +172,10 @@ struct RoundShared {
     uint32_t redi[kWavesPerBlock];
     uint32_t scan[kWavesPerBlock];
     unsigned long long red2[kWavesPerBlock];
-    uint32_t abort, list_n, npick, mcount, pfront, pback, mfail, mtotal, msel;
+    uint32_t abort, list_n, npick, mcount, pfront, pback, mfail, tfail, mtotal, msel;
     uint32_t cmin[kWave];  // merge: true distances of one chunk of 64 positions (float bits)
     uint32_t hist[256];    // merge: candidates per key bucket
-    uint32_t my[5 * 8 + 2];  // this workgroup's slot payload (R <= 8)
+    uint32_t my[6 * 8 + 2];  // this workgroup's slot payload (R <= 8)
 };
 
 // Per-thread telemetry accumulators.
@@ -200,7 +203,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                              uint32_t &epoch, unsigned char *smem, RoundShared &sh, RoundTele &tl,
                              bool record_trace, bool clocks)
 {
-    constexpr int W = 5 * R + 2;  // words per slot
+    constexpr int W = 6 * R + 2;  // words per slot
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     // the wavefront index is uniform: as a scalar it keeps wave-strided loops
     // and their addressing off the exec mask
@@ -236,7 +239,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
     float *cz = cy + G * R;
     float *cld = cz + G * R;  // local d2 (the selection d2 of a certified candidate)
     uint32_t *corig = reinterpret_cast<uint32_t *>(cld + G * R);
-    uint32_t *sidx = corig + G * R;  // merge order; its first P entries are the round's picks
+    uint32_t *crun = corig + G * R;  // distance bits of the runner-up at the candidate's lookahead step
+    uint32_t *sidx = crun + G * R;  // merge order; its first P entries are the round's picks
     float *px = reinterpret_cast<float *>(sidx + sort_cap(G, R));
 
     // ---- prologue: tile metadata and LDS offsets (block prefix sum) ----
@@ -337,13 +341,16 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             }
             for (int s = 0; s <= R; ++s) {
                 // arg max over the local tile keys (key and tile travel together)
-                unsigned long long lk = 0;
+                unsigned long long lk = 0, lk2 = 0;  // the lane's two largest tile keys
                 uint32_t lt_best = 0;
                 for (int lt = lane; lt < ntl; lt += kWave) {
                     const unsigned long long k = tkeyl[lt];
                     if (k > lk) {
+                        lk2 = lk;
                         lk = k;
                         lt_best = (uint32_t)lt;
+                    } else if (k > lk2) {
+                        lk2 = k;
                     }
                 }
                 const unsigned long long bk = wave_max_u64(lk);
@@ -351,23 +358,37 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 if (s == R || bk == 0) {
                     // the bound (or an empty workgroup): no more local candidates
                     if (lane == 0) {
-                        sh.my[5 * R] = (uint32_t)(bk >> 32);
-                        sh.my[5 * R + 1] = (uint32_t)bk;
+                        sh.my[6 * R] = (uint32_t)(bk >> 32);
+                        sh.my[6 * R + 1] = (uint32_t)bk;
                         for (int q = s; q < R; ++q)
-                            for (int w = 0; w < 5; ++w)
-                                sh.my[5 * q + w] = 0;
+                            for (int w = 0; w < 6; ++w)
+                                sh.my[6 * q + w] = 0;
                     }
                     break;
                 }
                 const uint32_t bt = (uint32_t)__builtin_amdgcn_readlane((int)lt_best, __ffsll((long long)hit) - 1);
                 const uint32_t p = tbestl[bt];
                 const float lx = px[p], ly = py[p], lz = pz[p];
+                // runner-up: the largest local key of any other point of this
+                // workgroup (other tiles, and the rest of the best tile); it
+                // bounds them if this candidate is not taken at its turn
+                unsigned long long ru = wave_max_u64(lk == bk ? lk2 : lk);
+                {
+                    const uint32_t meta = tmeta[bt];
+                    const uint32_t ls = meta & 0xffffu, cnt = meta >> 16;
+                    const bool valid = (uint32_t)lane < cnt;
+                    const uint32_t pp = ls + (valid ? lane : 0);
+                    const float dl = tflag[bt] ? pdl[pp] : pd[pp];
+                    const unsigned long long k = valid ? pack_key(dl, po[pp]) : 0ull;
+                    ru = umax64(ru, wave_max_u64(k == bk ? 0ull : k));
+                }
                 if (lane == 0) {
-                    sh.my[5 * s + 0] = __float_as_uint(lx);
-                    sh.my[5 * s + 1] = __float_as_uint(ly);
-                    sh.my[5 * s + 2] = __float_as_uint(lz);
-                    sh.my[5 * s + 3] = (uint32_t)(bk >> 32);  // local d2
-                    sh.my[5 * s + 4] = po[p];
+                    sh.my[6 * s + 0] = __float_as_uint(lx);
+                    sh.my[6 * s + 1] = __float_as_uint(ly);
+                    sh.my[6 * s + 2] = __float_as_uint(lz);
+                    sh.my[6 * s + 3] = (uint32_t)(bk >> 32);  // local d2
+                    sh.my[6 * s + 4] = po[p];
+                    sh.my[6 * s + 5] = (uint32_t)(ru >> 32);  // runner-up d2
                 }
                 // local update with l_s (pruned against the local thresholds)
                 for (int lt0 = 0; lt0 < ntl; lt0 += kWave) {
@@ -444,15 +465,15 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     return false;
                 const int e = tid + kBlock * r, g = e / W, w = e % W;
                 const uint32_t v = (uint32_t)xr;
-                if (w < 5 * R) {
-                    // field f of candidate w / 5: x, y, z, local d2, index; the
-                    // arrays sit in LDS in that order (cx, cy, cz, cld, corig),
-                    // G * R words apart
-                    const int f = w % 5;
-                    reinterpret_cast<uint32_t *>(cx)[f * (G * R) + g * R + w / 5] = v;
+                if (w < 6 * R) {
+                    // field f of candidate w / 6: x, y, z, local d2, index,
+                    // runner-up d2; the arrays sit in LDS in that order (cx, cy,
+                    // cz, cld, corig, crun), G * R words apart
+                    const int f = w % 6;
+                    reinterpret_cast<uint32_t *>(cx)[f * (G * R) + g * R + w / 6] = v;
                 } else {
                     // the bound key: high half first (little-endian halves)
-                    reinterpret_cast<uint32_t *>(bkey + g * (R + 1) + R)[w == 5 * R ? 1 : 0] = v;
+                    reinterpret_cast<uint32_t *>(bkey + g * (R + 1) + R)[w == 6 * R ? 1 : 0] = v;
                 }
                 return true;
             };
@@ -787,8 +808,11 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                         const bool fail =
                             (uint32_t)lane < n && __uint_as_float(sh.cmin[lane]) != cld[ord[base + lane]];
                         const unsigned long long fm = __ballot(fail);
+                        const uint32_t first = fm ? (uint32_t)(__ffsll((long long)fm) - 1) : n;
                         if (lane == 0)
-                            sh.mfail = fm ? (uint32_t)(__ffsll((long long)fm) - 1) : n;
+                            sh.mfail = first;
+                        if ((uint32_t)lane == first)
+                            sh.tfail = sh.cmin[lane];  // the true distance of the first failure
                     }
                     __syncthreads();
                     const uint32_t ok = sh.mfail;
@@ -801,12 +825,28 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 }
                 return P;
             };
-            uint32_t P = certify(0, min(Lf, pmax));
-            if (P == Lf && P < pmax) {
-                // every position of the front part holds: order the part behind
-                // it (all its keys are smaller) and go on.  The staged pick
-                // coordinates share their words with the stored keys, so these
-                // keys are formed again from the candidates' distances and indices.
+            // Certify in order.  When the candidate at position P fails, its
+            // true distance t (exact for the picks so far) is known, and its
+            // group's other points are bounded by that candidate's runner-up:
+            // the bound S rises to it, the group's later candidates (whose
+            // local keys assumed this one picked) and every key <= S leave the
+            // list, the failed candidate goes back in with key t if t > S, and
+            // certification resumes at P.  Every listed key bounds its
+            // candidate's true key and S bounds every unlisted point, so the
+            // first listed candidate is the next selection whenever its true
+            // key equals its listed key.  The part behind the front is
+            // ordered when certification reaches it or a failure leaves part
+            // of it above S.
+            const unsigned long long kfront = L > Lf ? (unsigned long long)(hlo + (sh.msel << bshift)) << 32 : 0ull;
+            unsigned long long scur = smax;
+            uint32_t P = 0, lim_ord = Lf, nfail = 0;
+            bool back_alive = Lf < L;
+            uint32_t *tmp = ord + L;  // rebuild buffer (the key region holds 2 * G * (R + 1) words)
+            // ranks the part behind the front into ord[Lf, L) (all its keys are
+            // smaller).  The staged pick coordinates share their words with the
+            // stored keys, so these keys are formed again from the candidates'
+            // distances and indices.
+            auto rank_back = [&]() {
                 rank_range(
                     Lf, L,
                     [&](uint32_t i) {
@@ -814,7 +854,80 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                         return ((unsigned long long)__float_as_uint(cld[c]) << 32) | (~corig[c]);
                     },
                     [&](uint32_t i) { return __float_as_uint(cld[sidx[i]]); });
-                P = certify(P, pmax);
+            };
+            for (;;) {
+                const uint32_t lim = min(lim_ord, pmax);
+                P = certify(P, lim);
+                if (P == lim) {
+                    if (P == lim_ord && back_alive && P < pmax) {
+                        // the whole front holds: order the part behind it and
+                        // go on
+                        rank_back();
+                        lim_ord = L;
+                        back_alive = false;
+                        continue;
+                    }
+                    break;
+                }
+                const uint32_t cf = ord[P];
+                const float tf = __uint_as_float(sh.tfail);
+                const unsigned long long kt = ((unsigned long long)__float_as_uint(tf) << 32) | (~corig[cf]);
+                scur = umax64(scur, ((unsigned long long)crun[cf] << 32) | 0xffffffffull);
+                if (++nfail > kMaxFailures)
+                    break;
+                if (back_alive && scur < kfront) {
+                    // part of the rest can still be taken: order it behind the
+                    // front first (the front is still as ranked)
+                    rank_back();
+                    lim_ord = L;
+                }
+                back_alive = false;
+                __syncthreads();  // every thread has read ord[P]
+                if (wave == 0) {
+                    // stable compaction of ord(P, lim_ord) into tmp with cf inserted
+                    const uint32_t gf = cf / R, hf = cf % R;
+                    const bool put = kt > scur;
+                    bool placed = !put;
+                    uint32_t nk = 0, posc = 0;
+                    const unsigned long long below = lane ? (~0ull >> (kWave - lane)) : 0ull;
+                    for (uint32_t q0 = P + 1; q0 < lim_ord; q0 += kWave) {
+                        const uint32_t q = q0 + lane;
+                        const bool in = q < lim_ord;
+                        const uint32_t cq = in ? ord[q] : 0u;
+                        const unsigned long long kq =
+                            in ? ((unsigned long long)__float_as_uint(cld[cq]) << 32) | (~corig[cq]) : 0ull;
+                        const bool keep = in && kq > scur && !(cq / R == gf && cq % R > hf);
+                        const unsigned long long m = __ballot(keep);
+                        uint32_t shift = placed ? 1u : 0u;
+                        if (!placed) {
+                            const unsigned long long lm = __ballot(keep && kq < kt);
+                            if (lm) {
+                                const int first = __ffsll((long long)lm) - 1;
+                                posc = nk + (uint32_t)__popcll(m & (first ? (~0ull >> (kWave - first)) : 0ull));
+                                placed = true;
+                                shift = lane >= first ? 1u : 0u;
+                            }
+                        }
+                        if (keep)
+                            tmp[nk + (uint32_t)__popcll(m & below) + (put ? shift : 0u)] = cq;
+                        nk += (uint32_t)__popcll(m);
+                    }
+                    if (put && !placed)
+                        posc = nk;  // below every kept key
+                    if (put && lane == 0)
+                        tmp[posc] = cf;
+                    const uint32_t nn = nk + (put ? 1u : 0u);
+                    for (uint32_t q = lane; q < nn; q += kWave)
+                        ord[P + q] = tmp[q];
+                    if (lane == 0) {
+                        sh.mtotal = P + nn;
+                        cld[cf] = tf;  // its listed key from now on
+                    }
+                }
+                __syncthreads();
+                lim_ord = sh.mtotal;
+                if (lim_ord == P)
+                    break;
             }
             if (tid == 0)
                 sh.npick = P;
