@@ -172,8 +172,8 @@ struct RoundShared {
     uint32_t redi[kWavesPerBlock];
     uint32_t scan[kWavesPerBlock];
     unsigned long long red2[kWavesPerBlock];
-    uint32_t abort, list_n, npick, mcount, pfront, pback, mfail, tfail, mtotal, msel;
-    uint32_t cmin[kWave];  // merge: true distances of one chunk of 64 positions (float bits)
+    uint32_t abort, list_n, npick, mcount, pfront, pback, mtotal, msel;
+    float cminw[2][kWavesPerBlock][kWave];  // merge: partial true distances of one chunk of 64 positions
     uint32_t hist[256];    // merge: candidates per key bucket
     uint32_t my[6 * 8 + 2];  // this workgroup's slot payload (R <= 8)
 };
@@ -614,8 +614,6 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     atomicAdd(&sh.hist[((uint32_t)(k >> 32) - hlo) >> bshift], 1u);
                 }
             }
-            if (tid < kWave)
-                sh.cmin[tid] = 0x7f800000u;  // +inf: the chunk minima start here
             __syncthreads();
             const uint32_t L = sh.mcount;
             uint32_t Lf = L;
@@ -760,28 +758,41 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             const uint32_t pmax = min(min(L, (uint32_t)kMaxRoundPicks), (uint32_t)(job.m - j));
             // certifies positions [from, lim) of the order; returns the end of
             // the certified prefix
-            auto certify = [&](uint32_t from, uint32_t lim) -> uint32_t {
-                // coordinates in merge order (those of the certified prefix are the picks)
-                for (uint32_t e = from + tid; e < lim; e += kBlock) {
-                    const uint32_t c = ord[e];
-                    pkx[e] = cx[c];
-                    pky[e] = cy[c];
-                    pkz[e] = cz[c];
+            // certifies positions [from, lim) of the order (their coordinates
+            // staged unless `staged`); returns the end of the certified prefix,
+            // and at a failure its candidate and true distance (cfail, tfail).
+            // Every wave takes the earlier positions q = w mod 4 and writes its
+            // partial minima; after one barrier every wave combines them and
+            // finds the first failure itself.  The partial minima alternate
+            // between two buffers, so a wave that runs ahead into the next chunk
+            // cannot overwrite those still being read.
+            uint32_t cpar = 0, cfail = 0;
+            float tfail = 0.0f;
+            auto certify = [&](uint32_t from, uint32_t lim, bool staged) -> uint32_t {
+                if (!staged) {
+                    // coordinates in merge order (those of the certified prefix are the picks)
+                    for (uint32_t e = from + tid; e < lim; e += kBlock) {
+                        const uint32_t c = ord[e];
+                        pkx[e] = cx[c];
+                        pky[e] = cy[c];
+                        pkz[e] = cz[c];
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
                 uint32_t P = from;
                 for (uint32_t base = from; base < lim; base += kWave) {
                     const uint32_t n = min((uint32_t)kWave, lim - base);
                     // true distance of every position of the chunk: its local
                     // value, lowered by every earlier position (the earlier ones
                     // are all picks if this one is reached; the group's own ones
-                    // change nothing); wave w takes the earlier positions
-                    // q = w mod 4 (broadcast reads)
+                    // change nothing)
+                    const uint32_t e = base + lane;
+                    const bool in = (uint32_t)lane < n;
+                    const uint32_t ce = in ? ord[e] : 0u;
+                    const float le = in ? cld[ce] : INFINITY;
                     {
-                        const uint32_t e = base + lane;
-                        const bool in = (uint32_t)lane < n;
                         const float x = pkx[in ? e : base], y = pky[in ? e : base], z = pkz[in ? e : base];
-                        float t = in ? cld[ord[e]] : INFINITY;
+                        float t = le;
                         const uint32_t qend = base + n - 1;  // no position reaches past it
                         uint32_t q = wave;
                         for (; q + 3 * kWavesPerBlock < qend; q += 4 * kWavesPerBlock) {
@@ -800,28 +811,23 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                         for (; q < qend; q += kWavesPerBlock)
                             if (q < e)
                                 t = fminf(t, sqdist(x, y, z, pkx[q], pky[q], pkz[q]));
-                        if (in)
-                            atomicMin(&sh.cmin[lane], __float_as_uint(t));
+                        sh.cminw[cpar][wave][lane] = t;
                     }
                     __syncthreads();
-                    if (wave == 0) {
-                        const bool fail =
-                            (uint32_t)lane < n && __uint_as_float(sh.cmin[lane]) != cld[ord[base + lane]];
-                        const unsigned long long fm = __ballot(fail);
-                        const uint32_t first = fm ? (uint32_t)(__ffsll((long long)fm) - 1) : n;
-                        if (lane == 0)
-                            sh.mfail = first;
-                        if ((uint32_t)lane == first)
-                            sh.tfail = sh.cmin[lane];  // the true distance of the first failure
-                    }
-                    __syncthreads();
-                    const uint32_t ok = sh.mfail;
-                    if (tid < kWave)
-                        sh.cmin[tid] = 0x7f800000u;  // +inf for the next chunk
-                    P = base + ok;
-                    __syncthreads();
-                    if (ok < n)
+                    float tt = sh.cminw[cpar][0][lane];
+#pragma unroll
+                    for (int w = 1; w < kWavesPerBlock; ++w)
+                        tt = fminf(tt, sh.cminw[cpar][w][lane]);
+                    cpar ^= 1u;
+                    const unsigned long long fm = __ballot(in && tt != le);
+                    if (fm) {
+                        const int first = __ffsll((long long)fm) - 1;
+                        cfail = (uint32_t)__builtin_amdgcn_readlane((int)ce, first);
+                        tfail = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tt), first));
+                        P = base + (uint32_t)first;
                         break;
+                    }
+                    P = base + n;
                 }
                 return P;
             };
@@ -840,7 +846,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             const unsigned long long kfront = L > Lf ? (unsigned long long)(hlo + (sh.msel << bshift)) << 32 : 0ull;
             unsigned long long scur = smax;
             uint32_t P = 0, lim_ord = Lf, nfail = 0;
-            bool back_alive = Lf < L;
+            bool back_alive = Lf < L, staged = false;
             uint32_t *tmp = ord + L;  // rebuild buffer (the key region holds 2 * G * (R + 1) words)
             // ranks the part behind the front into ord[Lf, L) (all its keys are
             // smaller).  The staged pick coordinates share their words with the
@@ -857,20 +863,22 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             };
             for (;;) {
                 const uint32_t lim = min(lim_ord, pmax);
-                P = certify(P, lim);
+                P = certify(P, lim, staged);
+                staged = false;
                 if (P == lim) {
                     if (P == lim_ord && back_alive && P < pmax) {
                         // the whole front holds: order the part behind it and
                         // go on
                         rank_back();
                         lim_ord = L;
+                        staged = false;
                         back_alive = false;
                         continue;
                     }
                     break;
                 }
-                const uint32_t cf = ord[P];
-                const float tf = __uint_as_float(sh.tfail);
+                const uint32_t cf = cfail;
+                const float tf = tfail;
                 const unsigned long long kt = ((unsigned long long)__float_as_uint(tf) << 32) | (~corig[cf]);
                 scur = umax64(scur, ((unsigned long long)crun[cf] << 32) | 0xffffffffull);
                 if (++nfail > kMaxFailures)
@@ -882,7 +890,6 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     lim_ord = L;
                 }
                 back_alive = false;
-                __syncthreads();  // every thread has read ord[P]
                 if (wave == 0) {
                     // stable compaction of ord(P, lim_ord) into tmp with cf inserted
                     const uint32_t gf = cf / R, hf = cf % R;
@@ -916,16 +923,26 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                         posc = nk;  // below every kept key
                     if (put && lane == 0)
                         tmp[posc] = cf;
-                    const uint32_t nn = nk + (put ? 1u : 0u);
-                    for (uint32_t q = lane; q < nn; q += kWave)
-                        ord[P + q] = tmp[q];
                     if (lane == 0) {
-                        sh.mtotal = P + nn;
+                        sh.mtotal = P + nk + (put ? 1u : 0u);
                         cld[cf] = tf;  // its listed key from now on
                     }
                 }
                 __syncthreads();
                 lim_ord = sh.mtotal;
+                // the new order, and the coordinates of the positions this
+                // round may still certify
+                for (uint32_t e = P + tid; e < lim_ord; e += kBlock) {
+                    const uint32_t c = tmp[e - P];
+                    ord[e] = c;
+                    if (e < pmax) {
+                        pkx[e] = cx[c];
+                        pky[e] = cy[c];
+                        pkz[e] = cz[c];
+                    }
+                }
+                __syncthreads();
+                staged = true;
                 if (lim_ord == P)
                     break;
             }
