@@ -72,7 +72,7 @@ typedef struct rfps_params {
      * or half of them for the multi-pick sampler on clouds below 65,536 points. */
     int32_t groups;
     /* Lookahead depth of the multi-pick sampler: every workgroup proposes
-     * this many local candidates per exchange round; 2, 4 or 8 (0 = 2).
+     * this many local candidates per exchange round; 2, 3, 4 or 8 (0 = 2).
      * Output-neutral, like n_vox, tile and groups. */
     int32_t lookahead;
     /* RFPS_F_* bits. */
@@ -252,7 +252,7 @@ rfps_status rfps_read_plain_status(const void *ws, size_t ws_bytes, void *stream
  *   params    host, may be NULL.  n_vox: 0 = per-cloud default bins, else
  *             the same bins for every cloud; tile as for rfps_build_index;
  *             groups: workgroups per cloud (a divisor of the compute units of
- *             one XCD, at least 2; 0 = all of them); lookahead 2, 4 or 8 (0 =
+ *             one XCD, at least 2; 0 = all of them); lookahead 2, 3, 4 or 8 (0 =
  *             2).  RFPS_F_NO_PRUNE, RFPS_F_SINGLE_PICK and RFPS_F_TRACE are
  *             not available here (RFPS_ERR_UNSUPPORTED).
  *   ws        device workspace of rfps_batched_workspace_size() bytes,
@@ -285,7 +285,7 @@ rfps_status rfps_batched_read_telemetry(const void *ws, size_t ws_bytes, void *s
 /*
  * Autotuner for batched calls: times rfps_sample_batched on this batch for
  * every combination of groups (per_xcd, per_xcd/2, .. down to 4), lookahead
- * (2, 4, 8) and tile (32, 64) that `base` leaves at 0 (non-zero fields of
+ * (2, 3, 4, 8) and tile (32, 64) that `base` leaves at 0 (non-zero fields of
  * base are kept), `reps` timed runs each after one untimed run, and returns
  * the fastest by median in *best (host) and its median in *best_ms (host,
  * may be NULL).  Shapes the device cannot hold (RFPS_ERR_CAPACITY,

@@ -214,7 +214,7 @@ bool params_valid(const rfps_params *p)
         return true;
     return p->n_vox >= 0 && p->n_vox <= kMaxNVox && p->tile >= 0 && p->tile <= kWave && p->groups >= 0 &&
            p->groups <= kMaxGroups && (p->flags & ~kKnownFlags) == 0 &&
-           (p->lookahead == 0 || p->lookahead == 2 || p->lookahead == 4 || p->lookahead == 8) &&
+           (p->lookahead == 0 || (p->lookahead >= 2 && p->lookahead <= 4) || p->lookahead == 8) &&
            p->shell_spacing >= 0.0f;  // also rejects NaN
 }
 
@@ -618,7 +618,7 @@ rfps_status rfps_autotune_batched(const float *xyz, int32_t n, const int32_t *of
     for (int t = per_xcd; t >= 4; t /= 2)
         if (per_xcd % t == 0 && (!b0.groups || b0.groups == t))
             Ts.push_back(t);
-    for (int r : {2, 4, 8})
+    for (int r : {2, 3, 4, 8})
         if (!b0.lookahead || b0.lookahead == r)
             Rs.push_back(r);
     for (int t : {32, 64})

@@ -1133,6 +1133,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
 }
 
 template __global__ void k_rfps_rounds<2>(RoundArgs);
+template __global__ void k_rfps_rounds<3>(RoundArgs);
 template __global__ void k_rfps_rounds<4>(RoundArgs);
 template __global__ void k_rfps_rounds<8>(RoundArgs);
 
@@ -1244,6 +1245,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
 }
 
 template __global__ void k_rfps_rounds_batched<2>(RoundArgs);
+template __global__ void k_rfps_rounds_batched<3>(RoundArgs);
 template __global__ void k_rfps_rounds_batched<4>(RoundArgs);
 template __global__ void k_rfps_rounds_batched<8>(RoundArgs);
 
@@ -1254,10 +1256,12 @@ static const void *rounds_fn(int R, bool batched)
 {
     if (batched)
         return R == 2   ? reinterpret_cast<const void *>(k_rfps_rounds_batched<2>)
+               : R == 3 ? reinterpret_cast<const void *>(k_rfps_rounds_batched<3>)
                : R == 4 ? reinterpret_cast<const void *>(k_rfps_rounds_batched<4>)
                : R == 8 ? reinterpret_cast<const void *>(k_rfps_rounds_batched<8>)
                         : nullptr;
     return R == 2   ? reinterpret_cast<const void *>(k_rfps_rounds<2>)
+           : R == 3 ? reinterpret_cast<const void *>(k_rfps_rounds<3>)
            : R == 4 ? reinterpret_cast<const void *>(k_rfps_rounds<4>)
            : R == 8 ? reinterpret_cast<const void *>(k_rfps_rounds<8>)
                     : nullptr;

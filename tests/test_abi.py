@@ -50,11 +50,11 @@ def test_workspace_sizes(L):
     assert 0 < a < b and a % 256 == 0
     assert L.rfps_index_workspace_size(0, ctypes.byref(p)) == 0
     assert L.rfps_index_workspace_size(-5, None) == 0
-    for la in (2, 4, 8):
+    for la in (2, 3, 4, 8):
         ok = rf.rfps_params(n_vox=16, lookahead=la)
         assert L.rfps_index_workspace_size(1000, ctypes.byref(ok)) == a
     for bad in (rf.rfps_params(n_vox=2000), rf.rfps_params(n_vox=16, tile=65), rf.rfps_params(groups=257),
-                rf.rfps_params(flags=0x100), rf.rfps_params(n_vox=-1), rf.rfps_params(lookahead=3),
+                rf.rfps_params(flags=0x100), rf.rfps_params(n_vox=-1), rf.rfps_params(lookahead=5),
                 rf.rfps_params(lookahead=16), rf.rfps_params(lookahead=-1)):
         assert L.rfps_index_workspace_size(1000, ctypes.byref(bad)) == 0
     assert L.rfps_fps_plain_workspace_size(1000, 0) > 0
@@ -132,7 +132,7 @@ def test_batched_workspace_and_host_checks(L):
     assert L.rfps_batched_workspace_size(100000, 4097, None) == 0
     assert L.rfps_batched_workspace_size(10, 11, None) == 0
     assert L.rfps_batched_workspace_size(0, 1, None) == 0
-    assert L.rfps_batched_workspace_size(1000, 2, ctypes.byref(rf.rfps_params(lookahead=3))) == 0
+    assert L.rfps_batched_workspace_size(1000, 2, ctypes.byref(rf.rfps_params(lookahead=5))) == 0
     fake = ctypes.c_void_p(0x1000)
     out = ctypes.c_void_p(0x2000)
     args = dict(xyz=fake, n=100, off=fake, m=fake, st=None, b=4, mt=20, p=None, ws=fake, wsb=1 << 30, oi=out)

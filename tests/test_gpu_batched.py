@@ -62,7 +62,7 @@ def _small_batch(seed):
 
 
 @pytest.mark.parametrize("groups", [0, 2, 4, 8, 16])
-@pytest.mark.parametrize("lookahead", [2, 4, 8])
+@pytest.mark.parametrize("lookahead", [2, 3, 4, 8])
 def test_small_batch_partitions(rf, groups, lookahead):
     xyz, offsets, m, starts = _small_batch(3)
     _check(rf, xyz, offsets, m, starts, groups=groups, lookahead=lookahead)
@@ -200,7 +200,7 @@ def test_autotuner_keeps_result(rf):
     xyz, offsets, m = synth.batch(seed=4, b=5, n_hi=40000)
     chosen, ms, (idx, d2) = rf.autotune_batched(torch.from_numpy(xyz).to(dev), offsets, m, reps=1)
     assert ms > 0
-    assert chosen["groups"] in (4, 8, 16, 32) and chosen["lookahead"] in (2, 4, 8) and chosen["tile"] in (32, 64)
+    assert chosen["groups"] in (4, 8, 16, 32) and chosen["lookahead"] in (2, 3, 4, 8) and chosen["tile"] in (32, 64)
     ei, ed = _expect(xyz, offsets, m, None)
     assert np.array_equal(idx.cpu().numpy(), ei)
     assert np.array_equal(d2.cpu().numpy().view(np.uint32), ed.view(np.uint32))

@@ -60,7 +60,7 @@ def test_rfps_cube_partitions(oracle_lib):
         for tile in (0, 1, 7):
             idx = m.build_index(x, n_vox=n_vox, tile=tile)
             for g in (1, 3, 64, 0):
-                for la, fl in ((0, 0), (2, 0), (8, 0), (0, m.F_SINGLE_PICK)):
+                for la, fl in ((0, 0), (3, 0), (4, 0), (8, 0), (0, m.F_SINGLE_PICK)):
                     got = m.sample(idx, 1024, 0, groups=g, lookahead=la, flags=fl)
                     st = m.read_status(idx)
                     what = "n_vox=%d tile=%d g=%d lookahead=%d flags=%d" % (n_vox, tile, g, la, fl)
@@ -106,6 +106,8 @@ def test_room_full(oracle_lib):
     assert_same(m.fps(x, 20000, 0, n_vox=48, tile=32, groups=128), ref, "rfps n48 t32 g128")
     assert_same(m.fps(x, 20000, 0, groups=32, lookahead=8), ref, "rfps g32 lookahead 8")
     assert_same(m.fps(x, 20000, 0, groups=256, lookahead=2), ref, "rfps g256 lookahead 2")
+    assert_same(m.fps(x, 20000, 0, groups=256, lookahead=3), ref, "rfps g256 lookahead 3")
+    assert_same(m.fps(x, 20000, 0, groups=256, lookahead=4), ref, "rfps g256 lookahead 4")
     assert_same(m.fps(x, 20000, 0, flags=m.F_SINGLE_PICK), ref, "rfps single pick")
     assert_same(m.fps_plain(x, 20000, 0, variant=0), ref, "plain persistent")
 
@@ -183,6 +185,7 @@ def test_edge_cases(oracle_lib):
         for n_vox in (1, 8, 64):
             assert_same(m.fps(x, mm, s, n_vox=n_vox), ref, "%s n_vox=%d" % (name, n_vox))
         assert_same(m.fps(x, mm, s, groups=7, lookahead=2), ref, name + " g7 la2")
+        assert_same(m.fps(x, mm, s, groups=64, lookahead=4), ref, name + " g64 la4")
         assert_same(m.fps(x, mm, s, flags=m.F_SINGLE_PICK), ref, name + " single")
         assert_same(m.fps_plain(x, mm, s, variant=0), ref, name + " plain0")
         assert_same(m.fps_plain(x, mm, s, variant=1), ref, name + " plain1")
