@@ -11,10 +11,12 @@
 //
 //   L  lookahead: every workgroup runs R steps of FPS on its own points only
 //      (on the private copy, with the same spherical pruning), giving local
-//      candidates l_1..l_R with local keys k_1 > .. > k_R and the bound
-//      k_{R+1}, the largest local key left after them;
+//      candidates l_1..l_R with local keys k_1 > .. > k_R, the bound
+//      k_{R+1} (the largest local key left after them), and for every step h
+//      the runner-up u_h, the largest local key of the group's other points
+//      when l_h was chosen;
 //   X  exchange: each workgroup publishes its candidates (coordinates, local
-//      distance, original index) and k_{R+1};
+//      distance, original index, runner-up distance) and k_{R+1};
 //   M  merge: every workgroup replays the same deterministic merge.  Group g
 //      keeps a head h_g (how many of its candidates were taken).  Its bound
 //      B_g = k_{h_g+1} is an upper bound on the true key of every point of g:
@@ -26,10 +28,14 @@
 //      exactly the next FPS selection (the Sec. 3.1 rule; keys are unique).
 //      The local distance already includes the group's own earlier picks
 //      (those it skipped are at least as far), so the true distance is the
-//      local one lowered by the other groups' earlier picks;
-//      Otherwise the round ends.  This visits the candidates in descending
-//      order of local key, so the merge sorts them and certifies them in that
-//      order, all threads of the workgroup at once;
+//      local one lowered by the other groups' earlier picks.  When the head
+//      l_h of g fails this test, its true key t is known exactly, and the
+//      other points of g are bounded by u_h (their local keys at step h
+//      assumed only l_1..l_{h-1}, which are picks); the later candidates of g
+//      are dropped, l_h is listed again with key t, and the merge goes on
+//      under the larger bound.  The merge sorts the candidates above the
+//      largest bound, certifies them in that order with all threads of the
+//      workgroup, and at a failure re-lists and resumes;
 //   A  apply: all picks of the round update the true state (spherical test
 //      per tile and pick, point skip, strict update, tile-key resync).
 //
