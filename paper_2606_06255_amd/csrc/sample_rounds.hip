@@ -328,6 +328,20 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
     unsigned long long t_mark = 0;
     int j = 1;
     uint32_t round = 0;
+    uint32_t out_n = 0, out_j = 0;  // selections of the last merge not yet written out
+    // writes them (rank 0 only) from threads [t0, kBlock); the merge's order,
+    // indices and distances stay in LDS until the next exchange
+    auto write_out = [&](int t0) {
+        if (rank == 0) {
+            const uint32_t *mord = reinterpret_cast<const uint32_t *>(bkey);
+            for (uint32_t k = (uint32_t)(tid - t0); k < out_n; k += (uint32_t)(kBlock - t0)) {
+                const uint32_t c = mord[k];
+                job.out_idx[out_j + k] = (int32_t)corig[c];
+                if (job.out_d2)
+                    job.out_d2[out_j + k] = cld[c];
+            }
+        }
+    };
     while (j < job.m) {
         ++round;
         ++epoch;
@@ -338,6 +352,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         // inside it and its LDS operations complete in order, so the steps
         // need no workgroup barrier.  Lanes take tiles for the arg max and the
         // sphere tests; a tile that the test keeps is updated by all lanes.
+        if (wave != 0 && out_n)
+            write_out(kWave);
         if (wave == 0) {
             for (int lt = lane; lt < ntl; lt += kWave) {
                 tkeyl[lt] = tkey[lt];
@@ -435,6 +451,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             }
         }
         __syncthreads();
+        out_n = 0;
         if (clocks) {
             const unsigned long long t = wall_clock64();
             tl.ph[0] += t - t_mark;
@@ -954,14 +971,11 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             }
             if (tid == 0)
                 sh.npick = P;
-            if (rank == 0) {
-                for (uint32_t k = tid; k < P; k += kBlock) {
-                    const uint32_t c = ord[k];
-                    job.out_idx[j + k] = (int32_t)corig[c];
-                    if (job.out_d2)
-                        job.out_d2[j + k] = cld[c];
-                }
-            }
+            // the outputs are written by the idle wavefronts of the next
+            // lookahead (or after the last round), so that waiting for the
+            // stores never delays this workgroup's next publication
+            out_n = P;
+            out_j = (uint32_t)j;
         }
         __syncthreads();
         const int P = (int)sh.npick;
@@ -1070,6 +1084,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         if (clocks)
             tl.ph[3] += wall_clock64() - t_mark;
     }
+    if (out_n)
+        write_out(0);  // the last round's selections
     tl.rounds += round;
     __syncthreads();  // LDS is reused by the next cloud
     return true;
