@@ -584,12 +584,13 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         // =============== M: certified merge (whole workgroup) ===============
         // Candidates are taken in descending order of local key; each one is
         // certified when its true distance (its local distance lowered by
-        // every earlier pick of the round) still equals its local distance,
-        // and the round ends at the first one that is not.  Taking the group
-        // with the largest bound B_g at every step visits exactly this order
-        // until the largest published bound S* = max_g k_{R+1} is reached,
-        // where it stops as well; so the candidates above S* are compacted,
-        // put in order by counting and certified 64 positions at a time.
+        // every earlier pick of the round) still equals its local distance.
+        // Taking the group with the largest bound B_g at every step visits
+        // exactly this order until the largest published bound S* = max_g
+        // k_{R+1} is reached, where it stops; so the candidates above S* are
+        // compacted, put in order by counting and certified 64 positions at a
+        // time, and a failed candidate is re-listed (below) instead of ending
+        // the round.
         {
             unsigned long long smax = 0, hmax = 0;
 #pragma unroll
