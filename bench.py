@@ -152,17 +152,21 @@ def main():
     if st != 0:
         raise rf.RfpsError(st, "device status")
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    sev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]  # step boundaries
     t_all0, t_all1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t_all0.record(stream)
+    sev[0].record(stream)
     for k in range(args.steps):
         step(ev[k])
+        sev[k + 1].record(stream)
     t_all1.record(stream)
     torch.cuda.synchronize()
     wall1 = time.perf_counter()
     total_ms = t_all0.elapsed_time(t_all1)
     sample_ms = [a.elapsed_time(b) for a, b in ev]
+    step_ms = [sev[k].elapsed_time(sev[k + 1]) for k in range(args.steps)]
     ms_per_step = total_ms / args.steps
     st = rf.read_status(idx)
     if st != 0:
@@ -221,6 +225,8 @@ def main():
                    "groups": args.groups or (torch.cuda.get_device_properties(dev).multi_processor_count //
                                              (1 if N >= 65536 else 2))},
         "ms_per_cloud": ms_per_step,
+        "step_ms_percentiles": {"p10": float(np.percentile(step_ms, 10)), "p50": float(np.median(step_ms)),
+                                "p90": float(np.percentile(step_ms, 90))},
         "build_ms": build_ms,
         "sample_ms": float(np.mean(sample_ms)),
         "index": {"voxels": info["n_voxels"], "tiles": NT},
@@ -234,7 +240,8 @@ def main():
         "latency_floor_ms": float(np.median(ex_us)) * len(tr) / 1e3,
         "roofline": {"bound": "hbm", "kernel": "k_rfps_rounds<%d>" % (args.lookahead or 2), "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "alg_bytes_per_launch": alg_bytes, "source_digest": digest},
+                     "traffic": traffic, "alg_bytes_per_launch": alg_bytes,
+                     "alg_bytes_per_selection": alg_bytes / max(1, M - 1), "source_digest": digest},
     }
 
     # ---- comparators (untimed region, same cloud, same GPU) ----------------
@@ -326,11 +333,26 @@ def cpu_baseline(clouds, ms, gpu_idx, gpu_d2, seconds):
         same &= bool(np.array_equal(ri, gi[:mp]) and np.array_equal(rd.view(np.uint32), gd[:mp].view(np.uint32)))
     dt = time.perf_counter() - t0
     total = sum(m for m in ms)
+    # context: one host thread, plain FPS and the CPU RadiusFPS of the oracle
+    # package on the same prefix of the first cloud (about seconds / 4 each)
+    c0, m0 = clouds[0], ms[0]
+    mp1 = max(2, min(m0, int(round(min(1.0, 0.25 * seconds / max(per_pt_sel * threads * c0.shape[0] * (m0 - 1),
+                                                                     1e-9)) * m0))))
+    t1 = time.perf_counter()
+    pi, _ = oracle.fps(c0, mp1, 0, threads=1)
+    t_plain1 = time.perf_counter() - t1
+    from paper_2606_06255_amd import default_n_vox
+    t1 = time.perf_counter()
+    ci, _, _ = oracle.rfps_cpu(c0, mp1, 0, n_vox=default_n_vox(c0.shape[0]))
+    t_rfps1 = time.perf_counter() - t1
+    single = {"plain_fps_value": (mp1 - 1) / t_plain1, "radiusfps_value": (mp1 - 1) / t_rfps1,
+              "radiusfps_speedup": t_plain1 / t_rfps1, "selections": mp1 - 1,
+              "same_selections": bool(np.array_equal(pi, ci) and np.array_equal(pi, gpu_idx[0][:mp1]))}
     return {"value": sel / dt, "unit": "selected pts/s", "cores": threads, "kind": "oracle",
             "sample": "first %.1f%% of the selections of every cloud of the same workload (%d of %d selections, "
                       "%d cloud%s), plain O(N*M) FPS in C, OpenMP" % (100 * frac, sel, total - len(ms), len(ms),
                                                                       "s" if len(ms) > 1 else ""),
-            "seconds": dt, "bitexact_prefix": same}
+            "seconds": dt, "bitexact_prefix": same, "single_thread": single}
 
 
 def run_stages(args, rf, dev, stream):
