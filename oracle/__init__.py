@@ -7,7 +7,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 Contents
 --------
 ``fps``             plain FPS in C (Algorithm 1 of the paper, FP32 squared
-                    distance, strict update, lowest-index tie-break).
+                    distance, strict update, lowest-index tie-break);
+                    ``euclid=True`` uses the FP32 Euclidean distance (the
+                    rounded root of the squared one, Sec. 3.4.2).
 ``fps_numpy``       the same definition as a vectorised numpy loop (a second,
                     independent transcription used to cross-check the C code).
 ``fps_bruteforce``  the selection rule of Sec. 3.1 evaluated from scratch at
@@ -15,6 +17,8 @@ Contents
                     tiny clouds.
 ``fps_exact_int``   the paper's Euclidean definition on integer clouds with
                     exact integer arithmetic (no floating point at all).
+``sqrt_rn_exact``   correctly rounded FP32 square root by integer arithmetic
+                    (no library square root), for the Euclidean pins.
 ``rfps_cpu``        CPU RadiusFPS (Sec. 3) with telemetry; must equal ``fps``.
 ``voxelize``        the voxel grid of Sec. 3.2 (pmin, L, voxel id per point).
 """
@@ -74,6 +78,8 @@ def lib():
         vp = ctypes.c_void_p
         L.oracle_fps.argtypes = [vp, i64, i64, i64, vp, vp, ctypes.c_int]
         L.oracle_fps.restype = ctypes.c_int
+        L.oracle_fps_euclid.argtypes = [vp, i64, i64, i64, vp, vp, ctypes.c_int]
+        L.oracle_fps_euclid.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         L.rfps_cpu_sample.argtypes = [vp, i64, i64, i64, i32, i32, u32, vp, vp,
@@ -96,13 +102,17 @@ def _as_xyz(xyz):
     return a
 
 
-def fps(xyz, m: int, start: int = 0, threads: int = 1):
-    """Plain FPS oracle. Returns (idx int32 [m], d2 float32 [m])."""
+def fps(xyz, m: int, start: int = 0, threads: int = 1, euclid: bool = False):
+    """Plain FPS oracle. Returns (idx int32 [m], d2 float32 [m]).
+
+    With ``euclid`` the distances (state and output) are FP32 Euclidean
+    norms instead of squared distances.
+    """
     a = _as_xyz(xyz)
     idx = np.empty(m, dtype=np.int32)
     d2 = np.empty(m, dtype=np.float32)
-    rc = lib().oracle_fps(a.ctypes.data, a.shape[0], m, start, idx.ctypes.data, d2.ctypes.data,
-                          threads)
+    fn = lib().oracle_fps_euclid if euclid else lib().oracle_fps
+    rc = fn(a.ctypes.data, a.shape[0], m, start, idx.ctypes.data, d2.ctypes.data, threads)
     if rc:
         raise OracleError("oracle_fps returned %d" % rc)
     return idx, d2
@@ -153,8 +163,12 @@ def sqdist_np(P, s):
     return (sq[:, 0] + sq[:, 1]) + sq[:, 2]
 
 
-def fps_numpy(xyz, m: int, start: int = 0):
-    """Algorithm 1 as a numpy loop (update, then arg max; np.argmax returns the first maximum)."""
+def fps_numpy(xyz, m: int, start: int = 0, euclid: bool = False):
+    """Algorithm 1 as a numpy loop (update, then arg max; np.argmax returns the first maximum).
+
+    ``euclid``: distances are np.sqrt of the FP32 squared distance (IEEE
+    single-precision root, correctly rounded).
+    """
     P = _as_xyz(xyz)
     n = P.shape[0]
     D = np.full(n, np.inf, dtype=np.float32)
@@ -164,6 +178,8 @@ def fps_numpy(xyz, m: int, start: int = 0):
     last = start
     for j in range(1, m):
         t = sqdist_np(P, P[last])
+        if euclid:
+            t = np.sqrt(t)
         np.minimum(D, t, out=D)   # equal values are bitwise identical, so min == strict update
         b = int(np.argmax(D))
         idx[j], d2[j] = b, D[b]
@@ -171,12 +187,13 @@ def fps_numpy(xyz, m: int, start: int = 0):
     return idx, d2
 
 
-def fps_bruteforce(xyz, m: int, start: int = 0):
+def fps_bruteforce(xyz, m: int, start: int = 0, euclid: bool = False):
     """Selection rule of Sec. 3.1 from scratch: s_j = arg max_p min_{s in S_{j-1}} d(p, s).
 
     Every step recomputes the full point-to-chosen-set distance matrix (no
     incremental state), takes the row minimum, then the largest value with the
-    smallest index.  Tiny clouds only.
+    smallest index.  Tiny clouds only.  ``euclid``: every squared distance is
+    replaced by its correctly rounded root from ``sqrt_rn_exact``.
     """
     P = _as_xyz(xyz)
     chosen = [start]
@@ -186,6 +203,8 @@ def fps_bruteforce(xyz, m: int, start: int = 0):
         d = P[:, None, :] - S[None, :, :]          # [n, |S|, 3] float32
         sq = d * d
         dist = (sq[..., 0] + sq[..., 1]) + sq[..., 2]
+        if euclid:
+            dist = _roots_exact(dist)
         near = dist.min(axis=1)
         best = near.max()
         bi = int(np.flatnonzero(near == best)[0])
@@ -218,3 +237,40 @@ def fps_exact_int(pts, m: int, start: int = 0):
         outd.append(D[bi])
         last = bi
     return out, outd
+
+
+def _roots_exact(a):
+    """sqrt_rn_exact element-wise (each distinct value computed once)."""
+    a = np.asarray(a, dtype=np.float32)
+    u, inv = np.unique(a, return_inverse=True)
+    r = np.array([sqrt_rn_exact(v) for v in u], dtype=np.float32)
+    return r[inv].reshape(a.shape)
+
+
+def sqrt_rn_exact(v) -> np.float32:
+    """FP32 square root of a non-negative FP32 value, rounded to nearest, by integers.
+
+    v = N * 4^q exactly with an integer N of at least 100 bits, so
+    sqrt(v) = sqrt(N) * 2^q; the integer root s = isqrt(N) carries 50 or more
+    bits, and rounding s (with the discarded fraction known to be non-zero
+    unless s^2 = N) to 24 significant bits gives the correctly rounded root.
+    """
+    import math
+    v = float(np.float32(v))
+    if v == 0.0 or math.isinf(v):
+        return np.float32(v)
+    if not v > 0.0:
+        raise ValueError("negative or NaN input")
+    _, e = math.frexp(v)              # v = f * 2^e, 0.5 <= f < 1
+    q = (e - 120) // 2                # 4^q well below v's last bit: N >= 2^119
+    N = int(math.ldexp(v, -2 * q))    # exact: the scaled value is an integer
+    assert math.ldexp(float(N), 2 * q) == v
+    s = math.isqrt(N)
+    inexact = s * s != N
+    shift = s.bit_length() - 24
+    t, rem = s >> shift, s & ((1 << shift) - 1)
+    half = 1 << (shift - 1)
+    # the true root is s + f with 0 <= f < 1 (f > 0 iff inexact)
+    if rem > half or (rem == half and inexact) or (rem == half and not inexact and (t & 1)):
+        t += 1
+    return np.float32(math.ldexp(float(t), q + shift))

@@ -19,6 +19,11 @@
  *   - the update is strict: D[i] changes only when the new distance is
  *     smaller (Sec. 3.4.2, equality case).
  *
+ * oracle_fps_euclid is the same definition with the Euclidean distance of
+ * the update rule of Sec. 3.4.2: d(p, s) = sqrtf of the squared distance
+ * above, correctly rounded as IEEE 754 requires of sqrtf.  Its state and
+ * reported distances are these FP32 norms.
+ *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math [-fopenmp] -shared -fPIC
  */
 #include <math.h>
@@ -58,11 +63,12 @@ int oracle_num_threads(void)
  * xyz: [n][3] float32, row-major.  Writes out_idx[m] (original indices) and,
  * if out_d2 is not NULL, out_d2[m] (the selected point's D at selection).
  * threads <= 0 uses the OpenMP default; threads == 1 is single-threaded.
+ * euclid != 0 uses the Euclidean distance instead of its square.
  * Returns 0 on success, 1 on invalid arguments, 2 on a non-finite coordinate,
  * 3 when out of memory.
  */
-int oracle_fps(const float *xyz, int64_t n, int64_t m, int64_t start,
-               int32_t *out_idx, float *out_d2, int threads)
+static int fps_plain(const float *xyz, int64_t n, int64_t m, int64_t start,
+                     int32_t *out_idx, float *out_d2, int threads, int euclid)
 {
     if (!xyz || !out_idx || n < 1 || m < 1 || m > n || start < 0 || start >= n)
         return 1;
@@ -95,6 +101,8 @@ int oracle_fps(const float *xyz, int64_t n, int64_t m, int64_t start,
 #endif
         for (int64_t i = 0; i < n; ++i) {
             float t = sqdist(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], sx, sy, sz);
+            if (euclid)
+                t = sqrtf(t);
             if (t < D[i])
                 D[i] = t;
         }
@@ -133,4 +141,16 @@ int oracle_fps(const float *xyz, int64_t n, int64_t m, int64_t start,
     }
     free(D);
     return 0;
+}
+
+int oracle_fps(const float *xyz, int64_t n, int64_t m, int64_t start,
+               int32_t *out_idx, float *out_d2, int threads)
+{
+    return fps_plain(xyz, n, m, start, out_idx, out_d2, threads, 0);
+}
+
+int oracle_fps_euclid(const float *xyz, int64_t n, int64_t m, int64_t start,
+                      int32_t *out_idx, float *out_d2, int threads)
+{
+    return fps_plain(xyz, n, m, start, out_idx, out_d2, threads, 1);
 }

@@ -185,3 +185,139 @@ def test_argument_errors(oracle_lib):
     Q[4, 1] = np.inf
     with pytest.raises(oracle_lib.OracleError):
         oracle_lib.fps(Q, 3, 0)
+
+
+# ---------------------------------------------------------------------------
+# Euclidean mode: FPS over the FP32 norm (the rounded root of the squared
+# distance), the distance of the update rule of Sec. 3.4.2.
+# ---------------------------------------------------------------------------
+
+def test_sqrt_rn_exact_is_round_to_nearest(oracle_lib):
+    # Definition of rounding to nearest: r is the FP32 value whose neighbour
+    # midpoints bracket sqrt(v), i.e. lo^2 < v < hi^2, checked in exact
+    # rational arithmetic.  Covers subnormal inputs, powers of two (where the
+    # lower neighbour is closer) and the top of the range.
+    from fractions import Fraction
+    rng = np.random.default_rng(7)
+    vals = [np.float32(1.4e-45), np.float32(1.1754942e-38), np.float32(1.17549435e-38), np.float32(1.0),
+            np.float32(2.0), np.float32(4.0), np.float32(0.25), np.finfo(np.float32).max]
+    vals += list(rng.random(300, dtype=np.float32) * np.float32(4.0))
+    vals += list(np.float32(2.0) ** rng.integers(-140, 127, 300).astype(np.float32)
+                 * rng.random(300, dtype=np.float32).astype(np.float32) + np.float32(1e-45))
+    for v in vals:
+        v = np.float32(v)
+        r = oracle_lib.sqrt_rn_exact(v)
+        up = np.nextafter(r, np.float32(np.inf))
+        dn = np.nextafter(r, np.float32(0))
+        lo = (Fraction(float(dn)) + Fraction(float(r))) / 2
+        hi = (Fraction(float(r)) + Fraction(float(up))) / 2
+        assert lo * lo < Fraction(float(v)) < hi * hi, v
+    assert oracle_lib.sqrt_rn_exact(np.float32(0)) == 0
+    assert np.isinf(oracle_lib.sqrt_rn_exact(np.float32(np.inf)))
+
+
+def test_euclid_lattice_closed_form(oracle_lib):
+    # On the integer lattice 0..16 every squared distance is a perfect
+    # square, so the Euclidean order has no rounding and the picks are those
+    # of the squared form; the distances are the integer gaps.
+    x = np.arange(17, dtype=np.float32)
+    P = np.stack([x, 0 * x, 0 * x], 1)
+    idx, d = oracle_lib.fps(P, 17, 0, euclid=True)
+    assert idx.tolist() == [0, 16, 8, 4, 12, 2, 6, 10, 14, 1, 3, 5, 7, 9, 11, 13, 15]
+    assert d.tolist() == [np.inf, 16, 8, 4, 4, 2, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1, 1]
+
+
+def _rounding_tie_pair(seed):
+    """Two points at different FP32 squared distances from the origin whose
+    rounded roots are equal.  For p1 = (u, v, 0) with d2 = A and r the
+    rounded root of A, the axis point p2 = (r, 0, 0) has d2 = fl(r^2), whose
+    rounded root is r again (radix 2, round to nearest); it differs from A
+    for most u, v."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    while True:
+        u, v = rng.random(2, dtype=np.float32) + np.float32(0.5)
+        A = (u * u) + (v * v)
+        r = oracle.sqrt_rn_exact(A)
+        B = r * r
+        if A != B and oracle.sqrt_rn_exact(B) == r:
+            return (u, v), r, A, B
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_euclid_rounding_tie_takes_lower_index(oracle_lib, seed):
+    (u, v), r, A, B = _rounding_tie_pair(seed)
+    lo_pt, hi_pt = ((u, v, 0), (r, 0, 0)) if A < B else ((r, 0, 0), (u, v, 0))
+    # index 1 holds the smaller squared distance, index 2 the larger
+    P = np.array([(0, 0, 0), lo_pt, hi_pt], dtype=np.float32)
+    idx_sq, d_sq = oracle_lib.fps(P, 2, 0)
+    idx_eu, d_eu = oracle_lib.fps(P, 2, 0, euclid=True)
+    assert idx_sq.tolist() == [0, 2] and d_sq[1] == max(A, B)
+    assert idx_eu.tolist() == [0, 1] and d_eu[1] == r
+    assert same((idx_eu, d_eu), oracle_lib.fps_bruteforce(P, 2, 0, euclid=True))
+
+
+def test_euclid_bruteforce_tiny(oracle_lib):
+    rng = np.random.default_rng(4321)
+    diverged = 0
+    for t in range(240):
+        n = int(rng.integers(1, 41))
+        kind = t % 3
+        if kind == 0:
+            P = rng.random((n, 3), dtype=np.float32)
+        elif kind == 1:   # grid of step 0.1: equal real distances, unequal FP32 ones
+            P = rng.integers(-4, 5, size=(n, 3)).astype(np.float32) * np.float32(0.1)
+        else:             # wide dynamic range
+            P = (rng.normal(size=(n, 3)) * 10.0 ** rng.integers(-3, 4)).astype(np.float32)
+        m = int(rng.integers(1, n + 1))
+        s = int(rng.integers(0, n))
+        ref = oracle_lib.fps(P, m, s, euclid=True)
+        assert same(ref, oracle_lib.fps_bruteforce(P, m, s, euclid=True)), (t, n, m, s)
+        assert same(ref, oracle_lib.fps_numpy(P, m, s, euclid=True)), (t, n, m, s)
+        diverged += not np.array_equal(ref[0], oracle_lib.fps(P, m, s)[0])
+    assert diverged >= 10   # the cases really exercise rounding ties
+
+
+def test_euclid_against_squared_first_divergence(oracle_lib):
+    # The rounded root is non-decreasing, so the two orders agree up to the
+    # first pick where two squared distances share one rounded root; there
+    # the Euclidean form takes the lower index of the tied points, and until
+    # then its distances are the rounded roots of the squared ones.
+    rng = np.random.default_rng(11)
+    seen = 0
+    for t in range(8):
+        P = rng.integers(-40, 41, size=(3000, 3)).astype(np.float32) * np.float32(0.1)
+        m = 800
+        i_sq, d_sq = oracle_lib.fps(P, m, 0, threads=0)
+        i_eu, d_eu = oracle_lib.fps(P, m, 0, threads=0, euclid=True)
+        k = int(np.argmax(i_sq != i_eu)) if np.any(i_sq != i_eu) else m
+        assert np.array_equal(d_eu[1:k], oracle_lib._roots_exact(d_sq[1:k]))
+        if k < m:
+            seen += 1
+            # after k-1 equal picks both states are equal up to the root
+            S = P[i_sq[:k]]
+            dd = P[:, None, :] - S[None, :, :]
+            sq = dd * dd
+            D = ((sq[..., 0] + sq[..., 1]) + sq[..., 2]).min(axis=1)
+            R = oracle_lib._roots_exact(D)
+            top = R.max()
+            tied = np.flatnonzero(R == top)
+            assert i_eu[k] == tied[0] and d_eu[k] == top
+            assert D[i_sq[k]] == D.max() and i_sq[k] != tied[0]
+    assert seen >= 1
+
+
+def test_euclid_invariants_room(oracle_lib):
+    P = synth.room(3)[:12000]
+    m = 1500
+    idx, d = oracle_lib.fps(P, m, 0, threads=0, euclid=True)
+    assert idx[0] == 0 and np.isinf(d[0])
+    assert np.all(d[1:-1] >= d[2:])
+    assert len(set(idx.tolist())) == m
+    S = P[idx[:-1]]
+    near = np.full(P.shape[0], np.inf, np.float32)
+    for s in S:
+        dd = P - s
+        sq = dd * dd
+        near = np.minimum(near, np.sqrt((sq[:, 0] + sq[:, 1]) + sq[:, 2]))
+    assert near.max() == d[-1]
