@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--no-comparators", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=256, help="size of the copy kernel used to calibrate counters")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU time budget of the oracle baseline")
+    ap.add_argument("--distance", default="squared", choices=("squared", "euclid"),
+                    help="FPS over FP32 squared distances (default) or over their rounded roots (RFPS_F_SQRT); "
+                         "euclid is available for the single-cloud workloads")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -118,6 +121,9 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
 
+    if args.distance == "euclid" and args.workload in ("batch", "lidar_stages"):
+        print("--distance euclid is available for the single-cloud workloads", file=sys.stderr)
+        return 2
     if args.workload == "batch":
         result = run_batch(args, rf, dev, stream)
         print(json.dumps(result), flush=True)
@@ -134,13 +140,16 @@ def main():
     out_i = torch.empty(M, dtype=torch.int32, device=dev)
     out_d = torch.empty(M, dtype=torch.float32, device=dev)
     idx = rf.build_index(x, n_vox=n_vox)
+    euclid = args.distance == "euclid"
+    fdist = rf.F_SQRT if euclid else 0
 
     def step(with_sample_events=None):
         nonlocal idx
         idx = rf.build_index(x, n_vox=n_vox, reuse=idx)
         if with_sample_events is not None:
             with_sample_events[0].record(stream)
-        rf.sample(idx, M, 0, groups=args.groups, lookahead=args.lookahead, out_idx=out_i, out_d2=out_d)
+        rf.sample(idx, M, 0, groups=args.groups, lookahead=args.lookahead, flags=fdist, out_idx=out_i,
+                  out_d2=out_d)
         if with_sample_events is not None:
             with_sample_events[1].record(stream)
 
@@ -184,7 +193,7 @@ def main():
     torch.cuda.synchronize()
     build_ms = b0.elapsed_time(b1)
     info = rf.read_index_info(idx)
-    rf.sample(idx, M, 0, groups=args.groups, lookahead=args.lookahead, flags=rf.F_TELEMETRY | rf.F_TRACE,
+    rf.sample(idx, M, 0, groups=args.groups, lookahead=args.lookahead, flags=rf.F_TELEMETRY | rf.F_TRACE | fdist,
               out_idx=out_i, out_d2=out_d)
     tel = rf.read_telemetry(idx)
     tr, hz = rf.read_trace(idx)
@@ -204,7 +213,7 @@ def main():
     samp_s = float(np.mean(sample_ms)) / 1e3
     achieved = alg_bytes / samp_s / 1e9
     digest = source_digest()
-    traffic = stored_traffic(args.workload, digest)
+    traffic = None if euclid else stored_traffic(args.workload, digest)
     pruned_frac = 1.0 - tel["points_visited"] / max(1, tel["iters"] * N)
 
     result = {
@@ -222,6 +231,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "n_points": N,
                    "m": M, "start": 0, "n_vox": n_vox, "tile": 64, "lookahead": args.lookahead or 2,
+                   "distance": args.distance,
                    "groups": args.groups or (torch.cuda.get_device_properties(dev).multi_processor_count //
                                              (1 if N >= 65536 else 2))},
         "ms_per_cloud": ms_per_step,
@@ -238,14 +248,27 @@ def main():
                         "p90": float(np.percentile(ex_us, 90)), "round_p50": float(np.median(it_us)),
                         "note": "publish to merged outcome of workgroup 0, per exchange round"},
         "latency_floor_ms": float(np.median(ex_us)) * len(tr) / 1e3,
-        "roofline": {"bound": "hbm", "kernel": "k_rfps_rounds<%d>" % (args.lookahead or 2), "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": "k_rfps_rounds%s<%d>" % ("_euclid" if euclid else "",
+                                                                           args.lookahead or 2),
+                     "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "alg_bytes_per_launch": alg_bytes,
                      "alg_bytes_per_selection": alg_bytes / max(1, M - 1), "source_digest": digest},
     }
 
     # ---- comparators (untimed region, same cloud, same GPU) ----------------
-    if not args.no_comparators:
+    if not args.no_comparators and euclid:
+        # the plain kernels sample squared distances only; the ablation is the
+        # same sampler with one selection per exchange
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        rf.sample(idx, M, 0, groups=args.groups, flags=rf.F_SINGLE_PICK | fdist, out_idx=out_i, out_d2=out_d)
+        b.record(stream)
+        torch.cuda.synchronize()
+        result["comparators"] = {"rfps_single_pick_sample_ms": a.elapsed_time(b)}
+        result["bitexact_vs_single_pick"] = bool(np.array_equal(out_i.cpu().numpy(), got_i) and np.array_equal(
+            out_d.cpu().numpy().view(np.uint32), got_d.view(np.uint32)))
+    elif not args.no_comparators:
         ws = rf.PlainWorkspace(N, dev)
         best = None
         comps = {}
@@ -303,13 +326,13 @@ def main():
 
     # ---- CPU baseline: the oracle on the host cores, bounded prefix ---------
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline([P], [M], [got_i], [got_d], args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline([P], [M], [got_i], [got_d], args.cpu_seconds, euclid=euclid)
 
     print(json.dumps(result), flush=True)
     return 0
 
 
-def cpu_baseline(clouds, ms, gpu_idx, gpu_d2, seconds):
+def cpu_baseline(clouds, ms, gpu_idx, gpu_d2, seconds, euclid=False):
     """The oracle (plain O(N*M) FPS in C, OpenMP over the host cores) on a
     bounded prefix of every cloud's selections, about `seconds` of CPU time in
     all; the prefixes are also checked against the GPU's outputs."""
@@ -328,7 +351,7 @@ def cpu_baseline(clouds, ms, gpu_idx, gpu_d2, seconds):
     t0 = time.perf_counter()
     for c, m, gi, gd in zip(clouds, ms, gpu_idx, gpu_d2):
         mp = max(2, min(m, int(round(frac * m))))
-        ri, rd = oracle.fps(c, mp, 0, threads=0)
+        ri, rd = oracle.fps(c, mp, 0, threads=0, euclid=euclid)
         sel += mp - 1
         same &= bool(np.array_equal(ri, gi[:mp]) and np.array_equal(rd.view(np.uint32), gd[:mp].view(np.uint32)))
     dt = time.perf_counter() - t0
@@ -339,7 +362,7 @@ def cpu_baseline(clouds, ms, gpu_idx, gpu_d2, seconds):
     mp1 = max(2, min(m0, int(round(min(1.0, 0.25 * seconds / max(per_pt_sel * threads * c0.shape[0] * (m0 - 1),
                                                                      1e-9)) * m0))))
     t1 = time.perf_counter()
-    pi, _ = oracle.fps(c0, mp1, 0, threads=1)
+    pi, _ = oracle.fps(c0, mp1, 0, threads=1, euclid=euclid)
     t_plain1 = time.perf_counter() - t1
     from paper_2606_06255_amd import default_n_vox
     t1 = time.perf_counter()
@@ -347,7 +370,7 @@ def cpu_baseline(clouds, ms, gpu_idx, gpu_d2, seconds):
     t_rfps1 = time.perf_counter() - t1
     single = {"plain_fps_value": (mp1 - 1) / t_plain1, "radiusfps_value": (mp1 - 1) / t_rfps1,
               "radiusfps_speedup": t_plain1 / t_rfps1, "selections": mp1 - 1,
-              "same_selections": bool(np.array_equal(pi, ci) and np.array_equal(pi, gpu_idx[0][:mp1]))}
+              "same_selections": bool(np.array_equal(pi, gpu_idx[0][:mp1]) and (euclid or np.array_equal(pi, ci)))}
     return {"value": sel / dt, "unit": "selected pts/s", "cores": threads, "kind": "oracle",
             "sample": "first %.1f%% of the selections of every cloud of the same workload (%d of %d selections, "
                       "%d cloud%s), plain O(N*M) FPS in C, OpenMP" % (100 * frac, sel, total - len(ms), len(ms),

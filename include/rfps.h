@@ -58,6 +58,12 @@ typedef enum rfps_status {
 #define RFPS_F_TELEMETRY 0x04u     /* count tests, prunes, visits and updates */
 #define RFPS_F_TRACE 0x08u         /* time every exchange of workgroup 0 */
 #define RFPS_F_SINGLE_PICK 0x10u   /* one selection per exchange (no multi-pick rounds) */
+/* Euclidean distances: FPS over the correctly rounded FP32 root of each
+ * squared distance, the distance of the update rule of Sec. 3.4.2, instead
+ * of the squared value itself.  The two orders differ only where rounding
+ * the root merges two distinct squared distances into one value (a tie, then
+ * settled by the lower index).  out_d2 then holds Euclidean distances. */
+#define RFPS_F_SQRT 0x20u
 
 typedef struct rfps_params {
     /* Voxel bins per axis, n_vox of eq. voxel_size (Sec. 3.2); 1..1024.
@@ -169,7 +175,8 @@ rfps_status rfps_build_index(const float *xyz, int32_t n, const rfps_params *par
  *   params   host, may be NULL; only `groups` and `flags` are read.
  *   out_idx  device, int32 [m]: original indices of the samples in order.
  *   out_d2   device, float32 [m] or NULL: out_d2[0] = +inf; out_d2[j] is the
- *            squared distance of sample j to the nearest earlier sample.
+ *            squared distance of sample j to the nearest earlier sample
+ *            (with RFPS_F_SQRT the Euclidean distance, the rounded root).
  * Calls on the same workspace must not overlap (they share its buffers).
  */
 rfps_status rfps_sample(const rfps_index *index, int32_t m, int32_t start,
@@ -259,7 +266,7 @@ rfps_status rfps_read_plain_status(const void *ws, size_t ws_bytes, void *stream
  *             256-byte aligned; calls on one workspace must not overlap.
  *   out_idx   device, int32 [m_total]: the selections of cloud c at
  *             m[0] + .. + m[c-1] onwards, as indices local to the cloud.
- *   out_d2    device, float32 [m_total] or NULL: squared distances as for
+ *   out_d2    device, float32 [m_total] or NULL: distances as for
  *             rfps_sample, per cloud (each cloud's first entry is +inf).
  * The call allocates nothing and never waits for the device, so it may be
  * captured into a HIP graph (under capture the persistent kernel is an

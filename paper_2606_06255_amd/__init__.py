@@ -27,6 +27,7 @@ F_NO_POINT_SKIP = 0x02
 F_TELEMETRY = 0x04
 F_TRACE = 0x08
 F_SINGLE_PICK = 0x10
+F_SQRT = 0x20
 WS_ALIGN = 256
 
 

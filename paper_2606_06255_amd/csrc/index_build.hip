@@ -403,6 +403,16 @@ __global__ __launch_bounds__(kBlock) void k_gather_xyz(const float *__restrict__
         out[3 * (size_t)j + a] = ok ? xyz[3 * (size_t)i + a] : NAN;
 }
 
+// Euclidean mode: the sampler keeps squared class tops; the reported
+// distance is their correctly rounded root (the same root for every value of
+// a class).
+__global__ __launch_bounds__(kBlock) void k_sqrt_out(float *__restrict__ d, int m)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < m)
+        d[j] = sqrt_rn(d[j]);
+}
+
 }  // namespace rfps
 
 namespace rfps {
@@ -412,6 +422,12 @@ static inline int blocks_for(long long n, int per_block) { return (int)((n + per
 hipError_t launch_gather_xyz(const float *xyz, int n, const int32_t *idx, int m, float *out, hipStream_t s)
 {
     k_gather_xyz<<<blocks_for(m, kBlock), kBlock, 0, s>>>(xyz, n, idx, m, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sqrt_out(float *d, int m, hipStream_t s)
+{
+    k_sqrt_out<<<blocks_for(m, kBlock), kBlock, 0, s>>>(d, m);
     return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr uint32_t kKnownFlags =
-    RFPS_F_NO_PRUNE | RFPS_F_NO_POINT_SKIP | RFPS_F_TELEMETRY | RFPS_F_TRACE | RFPS_F_SINGLE_PICK;
+    RFPS_F_NO_PRUNE | RFPS_F_NO_POINT_SKIP | RFPS_F_TELEMETRY | RFPS_F_TRACE | RFPS_F_SINGLE_PICK | RFPS_F_SQRT;
 constexpr int kDefaultLookahead = 2;
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -354,6 +354,8 @@ rfps_status rfps_sample(const rfps_index *index, int32_t m, int32_t start, const
         return RFPS_ERR_UNSUPPORTED;
     const IndexView v = make_view(index->ws, index->n, index->n_vox, index->tile, index->shells);
     hipError_t e = launch_rfps_sample(v, m, start, L, out_idx, out_d2, static_cast<hipStream_t>(stream));
+    if (e == hipSuccess && out_d2 && (L.flags & RFPS_F_SQRT))
+        e = launch_sqrt_out(out_d2, m, static_cast<hipStream_t>(stream));
     if (e == hipErrorCooperativeLaunchTooLarge)
         return RFPS_ERR_UNSUPPORTED;
     return e == hipSuccess ? RFPS_OK : RFPS_ERR_DEVICE;
@@ -561,6 +563,8 @@ rfps_status rfps_sample_batched(const float *xyz, int32_t n, const int32_t *offs
     hipError_t e = launch_build_batch(v, xyz, s);
     if (e == hipSuccess)
         e = launch_rfps_rounds_batched(v, L, out_idx, out_d2, s);
+    if (e == hipSuccess && out_d2 && (flags & RFPS_F_SQRT))
+        e = launch_sqrt_out(out_d2, m_total, s);
     if (e == hipErrorCooperativeLaunchTooLarge)
         return RFPS_ERR_UNSUPPORTED;
     return e == hipSuccess ? RFPS_OK : RFPS_ERR_DEVICE;

@@ -122,7 +122,8 @@ int main(int argc, char **argv)
     if (argc > 1 && strcmp(argv[1], "--batch") == 0)
         return run_batch(argc, argv);
     if (argc < 3) {
-        fprintf(stderr, "usage: %s cloud.f32 m [steps] [n_vox] [groups] [plain_variant]\n", argv[0]);
+        fprintf(stderr, "usage: %s cloud.f32 m [steps] [n_vox] [groups] [plain_variant] [copy_mb] [flags]\n",
+                argv[0]);
         return 2;
     }
     FILE *f = fopen(argv[1], "rb");
@@ -144,6 +145,7 @@ int main(int argc, char **argv)
     const int steps = argc > 3 ? atoi(argv[3]) : 3;
     rfps_params p = {argc > 4 ? atoi(argv[4]) : 0, 0, argc > 5 ? atoi(argv[5]) : 0, 0, 0u, 0.0f};
     const int plain = argc > 6 ? atoi(argv[6]) : -1;
+    p.flags = argc > 8 ? (uint32_t)strtoul(argv[8], nullptr, 0) : 0u;  // RFPS_F_* bits of the sampler
 
     float *xyz, *d2;
     int32_t *idx;

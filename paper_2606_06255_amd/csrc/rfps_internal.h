@@ -131,6 +131,68 @@ __device__ __forceinline__ float sqdist(float px, float py, float pz, float sx, 
     return s + zz;
 }
 
+// Correctly rounded FP32 square root of x in [0, +inf] (NaN passes through).
+// The FP64 root rounded to FP32 is within one unit of the answer; it is then
+// checked against the rounding boundaries on either side, the midpoints
+// between r and its FP32 neighbours.  A midpoint has at most 25 significant
+// bits, so its FP64 square is exact and never an FP32 value: the comparisons
+// decide the rounding exactly and a tie cannot occur.
+__device__ __forceinline__ float sqrt_rn(float x)
+{
+    if (!(x > 0.0f) || x == INFINITY)
+        return x;
+    float r = (float)sqrt((double)x);
+    const double xd = (double)x;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const uint32_t rb = __float_as_uint(r);
+        const double up = 0.5 * ((double)r + (double)__uint_as_float(rb + 1u));
+        const double dn = 0.5 * ((double)r + (double)__uint_as_float(rb - 1u));
+        if (xd > up * up)
+            r = __uint_as_float(rb + 1u);
+        else if (xd < dn * dn)
+            r = __uint_as_float(rb - 1u);
+    }
+    return r;
+}
+
+// Euclidean mode (RFPS_F_SQRT).  Sec. 3.4.2 states the distance update with
+// the Euclidean norm; its FP32 value is the rounded root of d2.  The state
+// keeps squared values: every new d2 is replaced by the top of its class,
+// the largest FP32 value whose rounded root equals that of d2.  This map is
+// non-decreasing and idempotent, and two values share a class exactly when
+// their rounded roots are equal, so min, the strict update and the arg max
+// (lowest index among equals) over class tops follow FPS on rounded
+// Euclidean distances step for step.  A class top is >= d2, so each pruning
+// and point-skip test, which shows the fresh d2 cannot fall below the state,
+// shows the same for its class top.  The reported distance is the rounded
+// root of the state.
+__device__ __forceinline__ float sqrt_class_top(float x)
+{
+    if (!(x > 0.0f) || x == INFINITY)
+        return x;
+    const float r = sqrt_rn(x);
+    // the class is [.., b) with b = (midpoint of r and its upper neighbour)^2,
+    // exact in FP64 and not an FP32 value
+    const double up = 0.5 * ((double)r + (double)__uint_as_float(__float_as_uint(r) + 1u));
+    const double b = up * up;
+    if (b > 3.4028234663852886e38)
+        return 3.4028234663852886e38f;
+    float y = (float)b;
+    if ((double)y > b)
+        y = __uint_as_float(__float_as_uint(y) - 1u);
+    return y;
+}
+
+// min(t, the state value of a fresh squared distance d2): the class top in
+// Euclidean mode (only needed when d2 < t, since the top is >= d2).
+__device__ __forceinline__ float min_dist(float t, float d2, bool euclid)
+{
+    if (euclid && d2 < t)
+        d2 = sqrt_class_top(d2);
+    return fminf(t, d2);
+}
+
 // Selection key: larger distance first, then the smaller original index.
 // For non-negative floats (including +inf) the bit pattern orders like the
 // value, so one unsigned 64-bit max realises the tie-break of Sec. 3.1.
@@ -378,6 +440,7 @@ __device__ __forceinline__ void publish_abort(unsigned long long *board, int G, 
 // ---------------------------------------------------------------------------
 hipError_t launch_build_index(const IndexView &v, const float *xyz, hipStream_t s);
 hipError_t launch_gather_xyz(const float *xyz, int n, const int32_t *idx, int m, float *out, hipStream_t s);
+hipError_t launch_sqrt_out(float *d, int m, hipStream_t s);
 hipError_t launch_scan(const uint32_t *in, uint32_t *out, int n, uint32_t *partials, uint32_t *total,
                        hipStream_t s);
 

@@ -115,6 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_rfps(SampleArgs a)
     const uint32_t NT = hdr->n_tiles;
     const int ntl = (NT > (uint32_t)g) ? (int)((NT - 1 - g) / G) + 1 : 0;
     const bool use_skip = !(a.flags & RFPS_F_NO_POINT_SKIP);
+    const bool euclid = (a.flags & RFPS_F_SQRT) != 0;
     const bool no_prune = (a.flags & RFPS_F_NO_PRUNE) != 0;
     const bool tele = (a.flags & RFPS_F_TELEMETRY) != 0;
     const bool trace = (a.flags & RFPS_F_TRACE) != 0 && g == 0 && tid == 0;
@@ -184,7 +185,8 @@ __global__ __launch_bounds__(kBlock) void k_rfps(SampleArgs a)
             const uint32_t i = gs + lane, p = ls + lane;
             const float x = a.xs[i], y = a.ys[i], z = a.zs[i];
             const uint32_t o = a.orig[i];
-            const float d = sqdist(x, y, z, sx, sy, sz);
+            const float d0 = sqdist(x, y, z, sx, sy, sz);
+            const float d = euclid ? sqrt_class_top(d0) : d0;
             px[p] = x;
             py[p] = y;
             pz[p] = z;
@@ -323,7 +325,9 @@ __global__ __launch_bounds__(kBlock) void k_rfps(SampleArgs a)
                 const float zz = dz * dz;
                 skip = use_skip && (xx >= d || yy >= d || zz >= d);
                 const float s2 = xx + yy;
-                const float t = s2 + zz;
+                float t = s2 + zz;
+                if (euclid && !skip && t < d)
+                    t = sqrt_class_top(t);
                 upd = !skip && t < d;
                 if (upd) {
                     d = t;

@@ -204,7 +204,7 @@ struct CloudJob {
 // Samples one cloud.  Every thread of every workgroup of the team calls it.
 // `epoch` is the team's exchange counter: it only grows, so slots never need
 // clearing between clouds.  Returns false when an exchange failed (abort).
-template <int R, Scope S>
+template <int R, Scope S, bool E>
 __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, int G, unsigned long long *board,
                              uint32_t &epoch, unsigned char *smem, RoundShared &sh, RoundTele &tl,
                              bool record_trace, bool clocks)
@@ -217,6 +217,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
     const uint32_t span = job.te - job.tb;
     const int ntl = (span > (uint32_t)rank) ? (int)((span - 1 - rank) / G) + 1 : 0;
     const bool use_skip = !(a.flags & RFPS_F_NO_POINT_SKIP);
+    constexpr bool euclid = E;  // Euclidean distances (RFPS_F_SQRT), a separate instantiation
     const bool tele = (a.flags & RFPS_F_TELEMETRY) != 0;
     const bool trace = record_trace && tid == 0;
 
@@ -313,7 +314,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 px[p] = x;
                 py[p] = y;
                 pz[p] = z;
-                pd[p] = sqdist(x, y, z, sx, sy, sz);
+                const float d0 = sqdist(x, y, z, sx, sy, sz);
+                pd[p] = euclid ? sqrt_class_top(d0) : d0;
                 po[p] = a.orig[i] - job.point_base;
             }
             tile_rekey(lane, lt, ls, c, pd, po, trad, tkey, tbest, tthr);
@@ -435,7 +437,9 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                             const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
                             const bool skip = use_skip && (xx >= d || yy >= d || zz >= d);
                             const float s2 = xx + yy;
-                            const float tt = s2 + zz;
+                            float tt = s2 + zz;
+                            if (euclid && !skip && tt < d)
+                                tt = sqrt_class_top(tt);
                             upd = !skip && tt < d;
                             if (upd) {
                                 d = tt;
@@ -830,11 +834,11 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
 #pragma unroll
                             for (int v = 0; v < 4; ++v)
                                 if (q + v * kWavesPerBlock < e)
-                                    t = fminf(t, sqdist(x, y, z, sx[v], sy[v], sz[v]));
+                                    t = min_dist(t, sqdist(x, y, z, sx[v], sy[v], sz[v]), euclid);
                         }
                         for (; q < qend; q += kWavesPerBlock)
                             if (q < e)
-                                t = fminf(t, sqdist(x, y, z, pkx[q], pky[q], pkz[q]));
+                                t = min_dist(t, sqdist(x, y, z, pkx[q], pky[q], pkz[q]), euclid);
                         sh.cminw[cpar][wave][lane] = t;
                     }
                     __syncthreads();
@@ -1058,7 +1062,9 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                             const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
                             const bool skip = use_skip && (xx >= d || yy >= d || zz >= d);
                             const float s2 = xx + yy;
-                            const float t = s2 + zz;
+                            float t = s2 + zz;
+                            if (euclid && !skip && t < d)
+                                t = sqrt_class_top(t);
                             if (!skip && t < d) {
                                 d = t;
                                 changed = true;
@@ -1116,8 +1122,8 @@ __device__ void flush_telemetry(IndexHeader *hdr, const RoundTele &tl, bool cloc
 // ---------------------------------------------------------------------------
 // Single cloud: one team made of the whole grid, agent-scope exchange.
 // ---------------------------------------------------------------------------
-template <int R>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rfps_rounds(RoundArgs a)
+template <int R, bool E>
+__device__ __forceinline__ void rounds_single(const RoundArgs &a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ RoundShared sh;
@@ -1141,7 +1147,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     job.out_d2 = a.out_d2;
     uint32_t epoch = 0;
     RoundTele tl;
-    const bool ok = sample_cloud<R, Scope::Agent>(a, job, blockIdx.x, a.G, a.board, epoch, smem, sh, tl,
+    const bool ok = sample_cloud<R, Scope::Agent, E>(a, job, blockIdx.x, a.G, a.board, epoch, smem, sh, tl,
                                                   (a.flags & RFPS_F_TRACE) != 0 && blockIdx.x == 0, clocks);
     if (tele && ok) {
         flush_telemetry(hdr, tl, clocks);
@@ -1155,10 +1161,27 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
         hdr->trace_n = (uint32_t)tl.rounds;
 }
 
+// Squared distances (the default) and Euclidean distances are separate
+// kernels, so the default one carries no code of the other form.
+template <int R>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rfps_rounds(RoundArgs a)
+{
+    rounds_single<R, false>(a);
+}
+template <int R>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rfps_rounds_euclid(RoundArgs a)
+{
+    rounds_single<R, true>(a);
+}
+
 template __global__ void k_rfps_rounds<2>(RoundArgs);
 template __global__ void k_rfps_rounds<3>(RoundArgs);
 template __global__ void k_rfps_rounds<4>(RoundArgs);
 template __global__ void k_rfps_rounds<8>(RoundArgs);
+template __global__ void k_rfps_rounds_euclid<2>(RoundArgs);
+template __global__ void k_rfps_rounds_euclid<3>(RoundArgs);
+template __global__ void k_rfps_rounds_euclid<4>(RoundArgs);
+template __global__ void k_rfps_rounds_euclid<8>(RoundArgs);
 
 // ---------------------------------------------------------------------------
 // Batches: teams of T workgroups, all on one XCD (found from the hardware
@@ -1170,8 +1193,8 @@ __device__ __forceinline__ uint32_t xcc_id()
     return __builtin_amdgcn_s_getreg((20) | (0 << 6) | ((16 - 1) << 11)) & 0xffu;
 }
 
-template <int R>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rfps_rounds_batched(RoundArgs a)
+template <int R, bool E>
+__device__ __forceinline__ void rounds_batched(const RoundArgs &a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ RoundShared sh;
@@ -1257,7 +1280,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
         job.start = bc.starts ? bc.starts[c] : 0;
         job.out_idx = a.out_idx + bc.out_offsets[c];
         job.out_d2 = a.out_d2 ? a.out_d2 + bc.out_offsets[c] : nullptr;
-        if (!sample_cloud<R, Scope::Xcd>(a, job, rank, T, board, epoch, smem, sh, tl, false, false))
+        if (!sample_cloud<R, Scope::Xcd, E>(a, job, rank, T, board, epoch, smem, sh, tl, false, false))
             return;
     }
     if (tele) {
@@ -1267,34 +1290,48 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     }
 }
 
+template <int R>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rfps_rounds_batched(RoundArgs a)
+{
+    rounds_batched<R, false>(a);
+}
+template <int R>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void
+k_rfps_rounds_batched_euclid(RoundArgs a)
+{
+    rounds_batched<R, true>(a);
+}
+
 template __global__ void k_rfps_rounds_batched<2>(RoundArgs);
 template __global__ void k_rfps_rounds_batched<3>(RoundArgs);
 template __global__ void k_rfps_rounds_batched<4>(RoundArgs);
 template __global__ void k_rfps_rounds_batched<8>(RoundArgs);
+template __global__ void k_rfps_rounds_batched_euclid<2>(RoundArgs);
+template __global__ void k_rfps_rounds_batched_euclid<3>(RoundArgs);
+template __global__ void k_rfps_rounds_batched_euclid<4>(RoundArgs);
+template __global__ void k_rfps_rounds_batched_euclid<8>(RoundArgs);
 
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
-static const void *rounds_fn(int R, bool batched)
+static const void *rounds_fn(int R, bool batched, bool euclid)
 {
+#define RFPS_ROUNDS_FN(K)                                                                                    \
+    (R == 2 ? reinterpret_cast<const void *>(K<2>) : R == 3 ? reinterpret_cast<const void *>(K<3>)          \
+     : R == 4                                            ? reinterpret_cast<const void *>(K<4>)            \
+     : R == 8                                            ? reinterpret_cast<const void *>(K<8>)            \
+                                                         : nullptr)
     if (batched)
-        return R == 2   ? reinterpret_cast<const void *>(k_rfps_rounds_batched<2>)
-               : R == 3 ? reinterpret_cast<const void *>(k_rfps_rounds_batched<3>)
-               : R == 4 ? reinterpret_cast<const void *>(k_rfps_rounds_batched<4>)
-               : R == 8 ? reinterpret_cast<const void *>(k_rfps_rounds_batched<8>)
-                        : nullptr;
-    return R == 2   ? reinterpret_cast<const void *>(k_rfps_rounds<2>)
-           : R == 3 ? reinterpret_cast<const void *>(k_rfps_rounds<3>)
-           : R == 4 ? reinterpret_cast<const void *>(k_rfps_rounds<4>)
-           : R == 8 ? reinterpret_cast<const void *>(k_rfps_rounds<8>)
-                    : nullptr;
+        return euclid ? RFPS_ROUNDS_FN(k_rfps_rounds_batched_euclid) : RFPS_ROUNDS_FN(k_rfps_rounds_batched);
+    return euclid ? RFPS_ROUNDS_FN(k_rfps_rounds_euclid) : RFPS_ROUNDS_FN(k_rfps_rounds);
+#undef RFPS_ROUNDS_FN
 }
 
 size_t rfps_rounds_static_lds(int R)
 {
     size_t mx = 0;
-    for (int b = 0; b < 2; ++b) {
-        const void *fn = rounds_fn(R, b == 1);
+    for (int b = 0; b < 4; ++b) {
+        const void *fn = rounds_fn(R, (b & 1) != 0, (b & 2) != 0);
         hipFuncAttributes attr;
         if (!fn || hipFuncGetAttributes(&attr, fn) != hipSuccess)
             return 0;
@@ -1343,7 +1380,7 @@ hipError_t launch_rfps_rounds(const IndexView &v, int m, int start, const Sample
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || m <= 1)
         return e;
-    const void *fn = rounds_fn(L.R, false);
+    const void *fn = rounds_fn(L.R, false, (L.flags & RFPS_F_SQRT) != 0);
     if (!fn)
         return hipErrorInvalidValue;
     RoundArgs a = round_args(v, m, start, L, out_idx, out_d2);
@@ -1395,7 +1432,7 @@ hipError_t launch_rfps_rounds_batched(const IndexView &v, const SampleLaunch &L,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    const void *fn = rounds_fn(L.R, true);
+    const void *fn = rounds_fn(L.R, true, (L.flags & RFPS_F_SQRT) != 0);
     if (!fn)
         return hipErrorInvalidValue;
     RoundArgs a = round_args(v, 0, 0, L, out_idx, out_d2);
