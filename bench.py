@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--no-comparators", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=256, help="size of the copy kernel used to calibrate counters")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU time budget of the oracle baseline")
+    ap.add_argument("--ablation", action="store_true",
+                    help="also time the sampler variants of the paper's ablation (pruning, point skip, one "
+                         "persistent kernel vs two launches per selection) on the same index")
     ap.add_argument("--distance", default="squared", choices=("squared", "euclid"),
                     help="FPS over FP32 squared distances (default) or over their rounded roots (RFPS_F_SQRT); "
                          "euclid is available for the single-cloud workloads")
@@ -316,6 +319,9 @@ def main():
         result["speedup_vs_plain_one_workgroup"] = one_wg_ms / ms_per_step
         result["bitexact_vs_plain"] = bool(same and same_1wg and same_single)
 
+    if args.ablation:
+        result["ablation"] = run_ablation(rf, idx, M, fdist, got_i, got_d, stream, torch, np)
+
     # ---- counter calibration: a plain copy of known size ---------------------
     nbytes = args.copy_mb << 20
     src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
@@ -330,6 +336,37 @@ def main():
 
     print(json.dumps(result), flush=True)
     return 0
+
+
+def run_ablation(rf, idx, M, fdist, got_i, got_d, stream, torch, np):
+    """Sampling time of each variant of the paper's ablation on the same index
+    (untimed region of the benchmark; the index build is not included)."""
+    variants = [
+        ("multi_pick", 0),
+        ("one_pick", rf.F_SINGLE_PICK),
+        ("one_pick_no_skip", rf.F_SINGLE_PICK | rf.F_NO_POINT_SKIP),
+        ("one_pick_no_prune", rf.F_NO_PRUNE),
+        ("one_pick_no_prune_no_skip", rf.F_NO_PRUNE | rf.F_NO_POINT_SKIP),
+        ("unfused", rf.F_UNFUSED),
+        ("unfused_no_skip", rf.F_UNFUSED | rf.F_NO_POINT_SKIP),
+        ("unfused_no_prune", rf.F_UNFUSED | rf.F_NO_PRUNE),
+        ("unfused_no_prune_no_skip", rf.F_UNFUSED | rf.F_NO_PRUNE | rf.F_NO_POINT_SKIP),
+    ]
+    out = {"note": "sample call only, index reused; one_pick = one persistent kernel with one exchange per "
+                   "selection (the paper's fused design); unfused = two launches per selection; "
+                   "no_prune = every tile visited; no_skip = no coordinate-wise point skip"}
+    for name, fl in variants:
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        oi, od = rf.sample(idx, M, 0, flags=fl | fdist)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        same = bool(np.array_equal(oi.cpu().numpy(), got_i) and
+                    np.array_equal(od.cpu().numpy().view(np.uint32), got_d.view(np.uint32)))
+        out[name] = {"sample_ms": ms, "bitexact": same}
+        log("ablation %-26s %10.2f ms  bitexact %s" % (name, ms, same))
+    return out
 
 
 def cpu_baseline(clouds, ms, gpu_idx, gpu_d2, seconds, euclid=False):

@@ -64,6 +64,13 @@ typedef enum rfps_status {
  * the root merges two distinct squared distances into one value (a tie, then
  * settled by the lower index).  out_d2 then holds Euclidean distances. */
 #define RFPS_F_SQRT 0x20u
+/* Unfused sampler (rfps_sample only): every selection is its own pair of
+ * kernel launches, a selection kernel and a filter/update/resync kernel,
+ * ordered by the stream, with the state in device memory between them: the
+ * per-iteration-launch variant of the paper's ablation (Sec. 4).  Same
+ * output; NO_PRUNE, NO_POINT_SKIP and SQRT apply, TELEMETRY and TRACE are
+ * not available with it (RFPS_ERR_UNSUPPORTED). */
+#define RFPS_F_UNFUSED 0x40u
 
 typedef struct rfps_params {
     /* Voxel bins per axis, n_vox of eq. voxel_size (Sec. 3.2); 1..1024.

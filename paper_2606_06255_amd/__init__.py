@@ -28,6 +28,7 @@ F_TELEMETRY = 0x04
 F_TRACE = 0x08
 F_SINGLE_PICK = 0x10
 F_SQRT = 0x20
+F_UNFUSED = 0x40
 WS_ALIGN = 256
 
 

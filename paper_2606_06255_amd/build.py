@@ -17,7 +17,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librfps.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["rfps_api.hip", "index_build.hip", "sample_rfps.hip", "sample_rounds.hip", "sample_plain.hip", "mlp.hip"]
+SOURCES = ["rfps_api.hip", "index_build.hip", "sample_rfps.hip", "sample_rounds.hip", "sample_plain.hip", "sample_unfused.hip",
+           "mlp.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -18,7 +18,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr uint32_t kKnownFlags =
-    RFPS_F_NO_PRUNE | RFPS_F_NO_POINT_SKIP | RFPS_F_TELEMETRY | RFPS_F_TRACE | RFPS_F_SINGLE_PICK | RFPS_F_SQRT;
+    RFPS_F_NO_PRUNE | RFPS_F_NO_POINT_SKIP | RFPS_F_TELEMETRY | RFPS_F_TRACE | RFPS_F_SINGLE_PICK | RFPS_F_SQRT | RFPS_F_UNFUSED;
 constexpr int kDefaultLookahead = 2;
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -328,6 +328,8 @@ rfps_status rfps_sample(const rfps_index *index, int32_t m, int32_t start, const
         return st;
     if (m < 1 || m > index->n || start < 0 || start >= index->n || !out_idx || !params_valid(params))
         return RFPS_ERR_INVALID_ARG;
+    if (params && (params->flags & RFPS_F_UNFUSED) && (params->flags & (RFPS_F_TELEMETRY | RFPS_F_TRACE)))
+        return RFPS_ERR_UNSUPPORTED;
     const DeviceInfo *d = device_info();
     if (!d)
         return RFPS_ERR_DEVICE;
@@ -524,7 +526,7 @@ rfps_status rfps_sample_batched(const float *xyz, int32_t n, const int32_t *offs
         batch > n || m_total < batch || m_total > n || !params_valid(params))
         return RFPS_ERR_INVALID_ARG;
     const uint32_t flags = params ? params->flags : 0u;
-    if (flags & (RFPS_F_NO_PRUNE | RFPS_F_SINGLE_PICK | RFPS_F_TRACE))
+    if (flags & (RFPS_F_NO_PRUNE | RFPS_F_SINGLE_PICK | RFPS_F_TRACE | RFPS_F_UNFUSED))
         return RFPS_ERR_UNSUPPORTED;
     const int fixed_n_vox = params ? params->n_vox : 0;
     const IndexLayout BL = layout_batch(n, batch, fixed_n_vox, use_shells(params));

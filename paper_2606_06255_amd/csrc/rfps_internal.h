@@ -454,6 +454,9 @@ struct SampleLaunch {
 size_t rfps_sampler_static_lds(int R);
 hipError_t launch_rfps_sample(const IndexView &v, int m, int start, const SampleLaunch &L, int32_t *out_idx,
                               float *out_d2, hipStream_t s);
+// The unfused sampler (sample_unfused.hip): two launches per selection.
+hipError_t launch_rfps_unfused(const IndexView &v, int m, int start, uint32_t flags, int32_t *out_idx,
+                               float *out_d2, hipStream_t s);
 // The multi-pick sampler (sample_rounds.hip); called by launch_rfps_sample.
 size_t rfps_rounds_static_lds(int R);
 hipError_t launch_rfps_rounds(const IndexView &v, int m, int start, const SampleLaunch &L, int32_t *out_idx,

@@ -397,7 +397,11 @@ hipError_t launch_rfps_sample(const IndexView &v, int m, int start, const Sample
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    if (L.R > 0) {
+    if (L.flags & RFPS_F_UNFUSED) {
+        e = launch_rfps_unfused(v, m, start, L.flags, out_idx, out_d2, s);
+        if (e != hipSuccess)
+            return e;
+    } else if (L.R > 0) {
         e = launch_rfps_rounds(v, m, start, L, out_idx, out_d2, s);
         if (e != hipSuccess)
             return e;

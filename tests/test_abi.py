@@ -94,6 +94,8 @@ def test_invalid_arguments_return_before_device_work(L):
     assert L.rfps_sample(ctypes.byref(h), 10, 100, None, out, None, None) == 1
     assert L.rfps_sample(ctypes.byref(h), 10, -1, None, out, None, None) == 1
     assert L.rfps_sample(ctypes.byref(h), 10, 0, None, None, None, None) == 1
+    for fl in (rf.F_UNFUSED | rf.F_TELEMETRY, rf.F_UNFUSED | rf.F_TRACE):
+        assert L.rfps_sample(ctypes.byref(h), 10, 0, ctypes.byref(rf.rfps_params(flags=fl)), out, None, None) == 5
     h.ws_bytes = 10
     assert L.rfps_sample(ctypes.byref(h), 10, 0, None, out, None, None) == 3
     h.ws = 0x1001
@@ -151,7 +153,7 @@ def test_batched_workspace_and_host_checks(L):
     assert call(mt=3) == 1        # fewer outputs than clouds
     assert call(mt=101) == 1      # more outputs than points
     assert call(n=0) == 1
-    for fl in (rf.F_NO_PRUNE, rf.F_SINGLE_PICK, rf.F_TRACE):
+    for fl in (rf.F_NO_PRUNE, rf.F_SINGLE_PICK, rf.F_TRACE, rf.F_UNFUSED):
         assert call(p=ctypes.byref(rf.rfps_params(flags=fl))) == 5
     assert call(ws=None) == 3
     assert call(ws=ctypes.c_void_p(0x1001)) == 3

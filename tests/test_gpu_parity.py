@@ -187,6 +187,7 @@ def test_edge_cases(oracle_lib):
         assert_same(m.fps(x, mm, s, groups=7, lookahead=2), ref, name + " g7 la2")
         assert_same(m.fps(x, mm, s, groups=64, lookahead=4), ref, name + " g64 la4")
         assert_same(m.fps(x, mm, s, flags=m.F_SINGLE_PICK), ref, name + " single")
+        assert_same(m.fps(x, mm, s, flags=m.F_UNFUSED), ref, name + " unfused")
         assert_same(m.fps_plain(x, mm, s, variant=0), ref, name + " plain0")
         assert_same(m.fps_plain(x, mm, s, variant=1), ref, name + " plain1")
 
@@ -207,6 +208,9 @@ def test_nonfinite_input_reports_and_poisons():
     x = dev(P)
     idx = m.build_index(x)
     oi, od = m.sample(idx, 64, 0)
+    assert m.read_status(idx) == 2
+    assert np.all(host(oi) == -1) and np.all(np.isnan(host(od)))
+    oi, od = m.sample(idx, 64, 0, flags=m.F_UNFUSED)
     assert m.read_status(idx) == 2
     assert np.all(host(oi) == -1) and np.all(np.isnan(host(od)))
     with pytest.raises(m.RfpsError) as e:
@@ -274,3 +278,32 @@ def test_trace_records_every_exchange():
     assert picks.sum() == 1023 and np.all(picks >= 1)
     t1 = tr[:, 1] & np.uint64((1 << 48) - 1)
     assert np.all(t1 >= tr[:, 0])
+
+
+def test_unfused_cube_and_room(oracle_lib):
+    # the per-iteration-launch sampler: every selection is its own pair of
+    # launches, with the state in device memory between them
+    m = rf()
+    P = synth.cube(4)
+    ref = oracle_lib.fps(P, 1024, 9)
+    ref_eu = oracle_lib.fps(P, 1024, 9, euclid=True)
+    x = dev(P)
+    for n_vox in (1, 4, 16):
+        for tile in (0, 1, 7):
+            idx = m.build_index(x, n_vox=n_vox, tile=tile)
+            for fl in (0, m.F_NO_PRUNE, m.F_NO_POINT_SKIP, m.F_NO_PRUNE | m.F_NO_POINT_SKIP):
+                what = "unfused n_vox=%d tile=%d flags=%d" % (n_vox, tile, fl)
+                assert_same(m.sample(idx, 1024, 9, flags=m.F_UNFUSED | fl), ref, what)
+                assert m.read_status(idx) == 0, what
+            assert_same(m.sample(idx, 1024, 9, flags=m.F_UNFUSED | m.F_SQRT), ref_eu, "unfused euclid")
+    R = synth.room(0)
+    ref = oracle_lib.fps(R, 20000, 0, threads=0)
+    xr = dev(R)
+    assert_same(m.fps(xr, 20000, 0, flags=m.F_UNFUSED), ref, "unfused room")
+    # the persistent samplers still work on an index the unfused one used
+    idx = m.build_index(xr)
+    assert_same(m.sample(idx, 20000, 0, flags=m.F_UNFUSED), ref, "unfused room, reused index")
+    assert_same(m.sample(idx, 20000, 0), ref, "multi-pick after unfused")
+    with pytest.raises(m.RfpsError) as e:
+        m.sample(idx, 100, 0, flags=m.F_UNFUSED | m.F_TELEMETRY)
+    assert e.value.status == 5
