@@ -100,6 +100,9 @@ def main():
     ap.add_argument("--ablation", action="store_true",
                     help="also time the sampler variants of the paper's ablation (pruning, point skip, one "
                          "persistent kernel vs two launches per selection) on the same index")
+    ap.add_argument("--cpu-sweep", action="store_true",
+                    help="also time the CPU RadiusFPS entry point for every voxel resolution of the default "
+                         "rule's candidate list, one thread and the default team (Sec. 5's sensitivity to v)")
     ap.add_argument("--distance", default="squared", choices=("squared", "euclid"),
                     help="FPS over FP32 squared distances (default) or over their rounded roots (RFPS_F_SQRT); "
                          "euclid is available for the single-cloud workloads")
@@ -333,9 +336,58 @@ def main():
     # ---- CPU baseline: the oracle on the host cores, bounded prefix ---------
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline([P], [M], [got_i], [got_d], args.cpu_seconds, euclid=euclid)
+        result["cpu_radiusfps"] = cpu_product(rf, P, M, fdist, got_i, got_d, np)
+    if args.cpu_sweep:
+        result["cpu_vox_sweep"] = cpu_vox_sweep(rf, P, M, fdist, got_i, np)
 
     print(json.dumps(result), flush=True)
     return 0
+
+
+def cpu_product(rf, P, M, fdist, got_i, got_d, np):
+    """The library's CPU RadiusFPS (rfps_cpu_sample, host cores, default
+    team) on the whole workload, and one thread on a prefix of it."""
+    t0 = time.perf_counter()
+    ci, cd = rf.cpu_fps(P, M, 0, flags=fdist)
+    dt = time.perf_counter() - t0
+    same = bool(np.array_equal(ci, got_i) and np.array_equal(cd.view(np.uint32), got_d.view(np.uint32)))
+    mp = min(M, 4096)
+    t0 = time.perf_counter()
+    si, _ = rf.cpu_fps(P, mp, 0, flags=fdist, threads=1)
+    dt1 = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    return {"value": (M - 1) / dt, "unit": "selected pts/s", "seconds": dt, "threads": threads,
+            "bitexact_vs_gpu": same,
+            "single_thread": {"value": (mp - 1) / dt1, "selections": mp - 1, "seconds": dt1,
+                              "same_prefix": bool(np.array_equal(si, got_i[:mp]))},
+            "note": "index build + sampling, host memory, synchronous"}
+
+
+def cpu_vox_sweep(rf, P, M, fdist, got_i, np):
+    """CPU RadiusFPS time per voxel resolution (one thread on a prefix of
+    min(M, 4096) selections, the default team on the whole workload)."""
+    out = {}
+    mp = min(M, 4096)
+    for v in (8, 12, 16, 24, 32, 48, 64, 96, 128, 192):
+        t0 = time.perf_counter()
+        ci, _ = rf.cpu_fps(P, M, 0, n_vox=v, flags=fdist)
+        team = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        si, _ = rf.cpu_fps(P, mp, 0, n_vox=v, flags=fdist, threads=1)
+        one = time.perf_counter() - t0
+        ok = bool(np.array_equal(ci, got_i) and np.array_equal(si, got_i[:mp]))
+        out[str(v)] = {"team_s": team, "one_thread_prefix_s": one, "bitexact": ok}
+        log("cpu sweep n_vox %4d: team %.3f s, one thread (%d selections) %.3f s, bitexact %s" % (v, team, mp - 1,
+                                                                                               one, ok))
+    teams = {}
+    for t in (1, 2, 4, 8, 16, 32):
+        t0 = time.perf_counter()
+        ci, _ = rf.cpu_fps(P, M, 0, flags=fdist, threads=t)
+        teams[str(t)] = time.perf_counter() - t0
+        log("cpu sweep default bins, %2d threads: %.3f s, bitexact %s" % (t, teams[str(t)],
+                                                                          bool(np.array_equal(ci, got_i))))
+    out["team_size_s"] = teams
+    return out
 
 
 def run_ablation(rf, idx, M, fdist, got_i, got_d, stream, torch, np):

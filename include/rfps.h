@@ -315,6 +315,31 @@ rfps_status rfps_autotune_batched(const float *xyz, int32_t n, const int32_t *of
                                   void *stream, rfps_params *best, float *best_ms);
 
 /* Static description of a status code. */
+/*
+ * CPU RadiusFPS (Sec. 3, the paper's CPU method) on the host cores: the
+ * same plain FPS sequence as the GPU samplers and the same readings (grid,
+ * enclosing spheres, FP-safe skip threshold, tie-break), run by a team of
+ * threads that each own every T-th tile and meet at one barrier per
+ * selection.
+ *   xyz      host, float32 [n][3]; 1 <= n <= 2^26.
+ *   m        samples, 1 <= m <= n; start as for rfps_sample.
+ *   params   host, may be NULL: n_vox (0 = half of rfps_default_n_vox(n),
+ *            at least 8: larger voxels suit the host's cores), tile
+ *            (0 = 64) and flags (RFPS_F_SQRT; RFPS_F_NO_POINT_SKIP is
+ *            accepted and changes nothing) are read.
+ *   threads  team size; 0 = OMP_NUM_THREADS if set, else the CPUs the
+ *            process may run on.  Each member spins at the barrier, so the
+ *            team should not exceed the cores available.
+ *   out_idx  host, int32 [m]; out_d2 host, float32 [m] or NULL (as for
+ *            rfps_sample).
+ * Synchronous; allocates host memory for its index and state (about 60
+ * bytes per point) and frees it before returning.  Non-finite input returns
+ * RFPS_ERR_NONFINITE with outputs -1 / NaN.
+ */
+rfps_status rfps_cpu_sample(const float *xyz, int32_t n, int32_t m, int32_t start,
+                            const rfps_params *params, int32_t threads, int32_t *out_idx,
+                            float *out_d2);
+
 const char *rfps_status_str(rfps_status s);
 
 /* Default voxel bins per axis for a cloud of n points. */

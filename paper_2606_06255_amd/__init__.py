@@ -95,6 +95,8 @@ def lib() -> ctypes.CDLL:
         L.rfps_fps_plain.restype = ctypes.c_int
         L.rfps_gather_xyz.argtypes = [vp, i32, vp, i32, vp, vp]
         L.rfps_gather_xyz.restype = ctypes.c_int
+        L.rfps_cpu_sample.argtypes = [vp, i32, i32, i32, P(rfps_params), i32, vp, vp]
+        L.rfps_cpu_sample.restype = ctypes.c_int
         L.rfps_read_plain_status.argtypes = [vp, sz, vp]
         L.rfps_read_plain_status.restype = ctypes.c_int
         L.rfps_batched_workspace_size.argtypes = [i32, i32, P(rfps_params)]
@@ -312,6 +314,24 @@ def gather_xyz(xyz: torch.Tensor, idx: torch.Tensor, out=None):
     _check(lib().rfps_gather_xyz(xyz.data_ptr(), xyz.shape[0], idx.data_ptr(), m, out.data_ptr(),
                                  _stream(xyz.device)), "rfps_gather_xyz")
     return out
+
+
+def cpu_fps(xyz, m: int, start: int = 0, n_vox: int = 0, tile: int = 0, flags: int = 0, threads: int = 0):
+    """rfps_cpu_sample: CPU RadiusFPS on the host cores.  xyz is a float32
+    [N, 3] array (numpy, or a CPU tensor); returns (idx int32 [m], d2 float32 [m])
+    as numpy arrays."""
+    import numpy as np
+    if isinstance(xyz, torch.Tensor):
+        xyz = xyz.detach().cpu().numpy()
+    a = np.ascontiguousarray(xyz, dtype=np.float32)
+    if a.ndim != 2 or a.shape[1] != 3:
+        raise ValueError("xyz must be [N, 3]")
+    idx = np.empty(m, dtype=np.int32)
+    d2 = np.empty(m, dtype=np.float32)
+    p = _params(n_vox, tile, flags=flags)
+    _check(lib().rfps_cpu_sample(a.ctypes.data, a.shape[0], int(m), int(start), ctypes.byref(p), int(threads),
+                                 idx.ctypes.data, d2.ctypes.data), "rfps_cpu_sample")
+    return idx, d2
 
 
 # ---------------------------------------------------------------------------
