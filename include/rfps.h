@@ -334,7 +334,8 @@ rfps_status rfps_autotune_batched(const float *xyz, int32_t n, const int32_t *of
  *            rfps_sample).
  * Synchronous; allocates host memory for its index and state (about 60
  * bytes per point) and frees it before returning.  Non-finite input returns
- * RFPS_ERR_NONFINITE with outputs -1 / NaN.
+ * RFPS_ERR_NONFINITE, and host memory or threads that cannot be obtained
+ * RFPS_ERR_INTERNAL; both leave the outputs -1 / NaN.
  */
 rfps_status rfps_cpu_sample(const float *xyz, int32_t n, int32_t m, int32_t start,
                             const rfps_params *params, int32_t threads, int32_t *out_idx,

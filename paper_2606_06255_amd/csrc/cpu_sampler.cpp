@@ -243,7 +243,8 @@ public:
             box_[i].epoch.store(0, std::memory_order_relaxed);
         }
     }
-    uint64_t all(int r, uint64_t v, uint64_t epoch)
+    // Returns early (with a partial maximum) once `abort` is set.
+    uint64_t all(int r, uint64_t v, uint64_t epoch, const std::atomic<bool> &abort)
     {
         Msg *b = box_.get() + (size_t)(epoch & 1) * rounds_ * T_;
         for (int k = 0; k < rounds_; ++k, b += T_) {
@@ -252,9 +253,12 @@ public:
             out.epoch.store(epoch, std::memory_order_release);
             Msg &in = b[r];
             int spins = 0;
-            while (in.epoch.load(std::memory_order_acquire) != epoch)
+            while (in.epoch.load(std::memory_order_acquire) != epoch) {
+                if (abort.load(std::memory_order_relaxed))
+                    return v;
                 if (++spins > 4096)
                     std::this_thread::yield();
+            }
             v = std::max(v, in.key.load(std::memory_order_relaxed));
         }
         return v;
@@ -280,6 +284,7 @@ struct Team {
     std::vector<float> pd;            // Dist_p, sorted order
     std::vector<Share> share;
     MaxReduce reduce;
+    std::atomic<bool> abort{false};   // set when the team could not be started
     int32_t *out_idx;
     float *out_d2;
     explicit Team(int t) : reduce(t) {}
@@ -324,7 +329,9 @@ void run_member(Team &tm, int r)
     for (int l = 0; l < nl; ++l)
         local = std::max(local, sh.key[l]);
     for (int j = 1; j < tm.m; ++j) {
-        const uint64_t best = tm.reduce.all(r, local, (uint64_t)j);
+        const uint64_t best = tm.reduce.all(r, local, (uint64_t)j, tm.abort);
+        if (tm.abort.load(std::memory_order_relaxed))
+            return;
         const uint32_t o = ~(uint32_t)best;
         const float d = bitsf((uint32_t)(best >> 32));
         if (r == 0) {
@@ -365,11 +372,17 @@ int default_team()
     return (int)std::max(1u, std::thread::hardware_concurrency());
 }
 
-}  // namespace
+void poison(int32_t *out_idx, float *out_d2, int m)
+{
+    for (int j = 0; j < m; ++j) {
+        out_idx[j] = -1;
+        if (out_d2)
+            out_d2[j] = std::nanf("");
+    }
+}
 
-extern "C" rfps_status rfps_cpu_sample(const float *xyz, int32_t n, int32_t m, int32_t start,
-                                       const rfps_params *params, int32_t threads, int32_t *out_idx,
-                                       float *out_d2)
+rfps_status cpu_sample(const float *xyz, int32_t n, int32_t m, int32_t start, const rfps_params *params,
+                       int32_t threads, int32_t *out_idx, float *out_d2)
 {
     if (!xyz || !out_idx || n < 1 || n > (1 << 26) || m < 1 || m > n || start < 0 || start >= n || threads < 0)
         return RFPS_ERR_INVALID_ARG;
@@ -384,11 +397,7 @@ extern "C" rfps_status rfps_cpu_sample(const float *xyz, int32_t n, int32_t m, i
         return RFPS_ERR_INVALID_ARG;
     for (size_t i = 0; i < 3 * (size_t)n; ++i)
         if (!std::isfinite(xyz[i])) {
-            for (int j = 0; j < m; ++j) {
-                out_idx[j] = -1;
-                if (out_d2)
-                    out_d2[j] = std::nanf("");
-            }
+            poison(out_idx, out_d2, m);
             return RFPS_ERR_NONFINITE;
         }
     Index I;
@@ -436,8 +445,17 @@ extern "C" rfps_status rfps_cpu_sample(const float *xyz, int32_t n, int32_t m, i
         out_d2[0] = INFINITY;
     std::vector<std::thread> pool;
     pool.reserve(T - 1);
-    for (int r = 1; r < T; ++r)
-        pool.emplace_back(run_member, std::ref(tm), r);
+    try {
+        for (int r = 1; r < T; ++r)
+            pool.emplace_back(run_member, std::ref(tm), r);
+    } catch (...) {
+        // a member could not be started: release the ones waiting for it
+        tm.abort.store(true);
+        for (auto &th : pool)
+            th.join();
+        poison(out_idx, out_d2, m);
+        return RFPS_ERR_INTERNAL;
+    }
     run_member(tm, 0);
     for (auto &th : pool)
         th.join();
@@ -445,4 +463,21 @@ extern "C" rfps_status rfps_cpu_sample(const float *xyz, int32_t n, int32_t m, i
         for (int j = 1; j < m; ++j)
             out_d2[j] = std::sqrt(out_d2[j]);
     return RFPS_OK;
+}
+
+}  // namespace
+
+extern "C" rfps_status rfps_cpu_sample(const float *xyz, int32_t n, int32_t m, int32_t start,
+                                       const rfps_params *params, int32_t threads, int32_t *out_idx,
+                                       float *out_d2)
+{
+    // no C++ exception may cross the C boundary: host memory that cannot be
+    // obtained is reported like a team that cannot be started
+    try {
+        return cpu_sample(xyz, n, m, start, params, threads, out_idx, out_d2);
+    } catch (...) {
+        if (out_idx && m >= 1 && m <= n)
+            poison(out_idx, out_d2, m);
+        return RFPS_ERR_INTERNAL;
+    }
 }
