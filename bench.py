@@ -102,7 +102,7 @@ def main():
                          "persistent kernel vs two launches per selection) on the same index")
     ap.add_argument("--cpu-sweep", action="store_true",
                     help="also time the CPU RadiusFPS entry point for every voxel resolution of the default "
-                         "rule's candidate list, one thread and the default team (Sec. 5's sensitivity to v)")
+                         "rule's candidate list, one thread and the default team (the sensitivity to v of Sec. 5.6.2)")
     ap.add_argument("--distance", default="squared", choices=("squared", "euclid"),
                     help="FPS over FP32 squared distances (default) or over their rounded roots (RFPS_F_SQRT); "
                          "euclid is available for the single-cloud workloads")
@@ -113,6 +113,9 @@ def main():
         print("bench.py runs on exactly one GPU: there is no multi-GPU path (batched clouds would shard "
               "across GPUs by cost with no exchange; a single cloud needs one exchange per round)",
               file=sys.stderr)
+        return 2
+    if args.distance == "euclid" and args.workload in ("batch", "lidar_stages"):
+        print("--distance euclid is available for the single-cloud workloads", file=sys.stderr)
         return 2
 
     import numpy as np
@@ -127,9 +130,6 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
 
-    if args.distance == "euclid" and args.workload in ("batch", "lidar_stages"):
-        print("--distance euclid is available for the single-cloud workloads", file=sys.stderr)
-        return 2
     if args.workload == "batch":
         result = run_batch(args, rf, dev, stream)
         print(json.dumps(result), flush=True)

@@ -59,7 +59,7 @@ typedef enum rfps_status {
 #define RFPS_F_TRACE 0x08u         /* time every exchange of workgroup 0 */
 #define RFPS_F_SINGLE_PICK 0x10u   /* one selection per exchange (no multi-pick rounds) */
 /* Euclidean distances: FPS over the correctly rounded FP32 root of each
- * squared distance, the distance of the update rule of Sec. 3.4.2, instead
+ * squared distance, the distance of the update rule of Sec. 3.4.3, instead
  * of the squared value itself.  The two orders differ only where rounding
  * the root merges two distinct squared distances into one value (a tie, then
  * settled by the lower index).  out_d2 then holds Euclidean distances. */
@@ -67,7 +67,7 @@ typedef enum rfps_status {
 /* Unfused sampler (rfps_sample only): every selection is its own pair of
  * kernel launches, a selection kernel and a filter/update/resync kernel,
  * ordered by the stream, with the state in device memory between them: the
- * per-iteration-launch variant of the paper's ablation (Sec. 4).  Same
+ * per-iteration-launch variant of the paper's ablation (Sec. 5.4).  Same
  * output; NO_PRUNE, NO_POINT_SKIP and SQRT apply, TELEMETRY and TRACE are
  * not available with it (RFPS_ERR_UNSUPPORTED). */
 #define RFPS_F_UNFUSED 0x40u

@@ -9,7 +9,7 @@ Contents
 ``fps``             plain FPS in C (Algorithm 1 of the paper, FP32 squared
                     distance, strict update, lowest-index tie-break);
                     ``euclid=True`` uses the FP32 Euclidean distance (the
-                    rounded root of the squared one, Sec. 3.4.2).
+                    rounded root of the squared one, Sec. 3.4.3).
 ``fps_numpy``       the same definition as a vectorised numpy loop (a second,
                     independent transcription used to cross-check the C code).
 ``fps_bruteforce``  the selection rule of Sec. 3.1 evaluated from scratch at

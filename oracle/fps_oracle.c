@@ -20,7 +20,8 @@
  *     smaller (Sec. 3.4.2, equality case).
  *
  * oracle_fps_euclid is the same definition with the Euclidean distance of
- * the update rule of Sec. 3.4.2: d(p, s) = sqrtf of the squared distance
+ * the update rule of Sec. 3.4.3 (eq. point_distance_update): d(p, s) = sqrtf
+ * of the squared distance
  * above, correctly rounded as IEEE 754 requires of sqrtf.  Its state and
  * reported distances are these FP32 norms.
  *

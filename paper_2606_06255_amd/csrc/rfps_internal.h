@@ -156,8 +156,8 @@ __device__ __forceinline__ float sqrt_rn(float x)
     return r;
 }
 
-// Euclidean mode (RFPS_F_SQRT).  Sec. 3.4.2 states the distance update with
-// the Euclidean norm; its FP32 value is the rounded root of d2.  The state
+// Euclidean mode (RFPS_F_SQRT).  Sec. 3.4.3 (eq. point_distance_update)
+// states the distance update with the Euclidean norm; its FP32 value is the rounded root of d2.  The state
 // keeps squared values: every new d2 is replaced by the top of its class,
 // the largest FP32 value whose rounded root equals that of d2.  This map is
 // non-decreasing and idempotent, and two values share a class exactly when

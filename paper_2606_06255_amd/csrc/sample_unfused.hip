@@ -1,15 +1,15 @@
 // Unfused sampler: one stream-ordered pair of kernel launches per selection.
 //
-// The paper's ablation (Sec. 4, Tab. ablation) compares its fused persistent
+// The paper's ablation (Sec. 5.4, Tab. ablation) compares its fused persistent
 // kernel with a variant that splits every iteration into separate kernels
 // (selection, voxel filter, point update, voxel resync).  This is that
 // variant on the same index: per selection j,
 //   k_unf_select  one workgroup takes the largest tile key (largest distance,
 //                 lowest original index), records s_j and writes the outputs;
 //   k_unf_update  a grid-stride pass over the tiles: spherical filter
-//                 (Sec. 3.4.1), point skip and strict update (Sec. 3.4.2 -
-//                 3.4.3), and the tile's key resync (Sec. 3.4.4), fused into
-//                 one launch since each needs only its own tile.
+//                 (Sec. 3.4.2), point skip, strict update and the tile's key
+//                 resync (Sec. 3.4.3), fused into one launch since each needs
+//                 only its own tile.
 // The state lives in HBM between launches: Dist_p in sorted order and the
 // tile keys as two 32-bit halves.  It reuses index buffers the build no
 // longer needs (the idle radix ping-pong buffer, the voxel head flags and

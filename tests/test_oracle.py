@@ -189,7 +189,7 @@ def test_argument_errors(oracle_lib):
 
 # ---------------------------------------------------------------------------
 # Euclidean mode: FPS over the FP32 norm (the rounded root of the squared
-# distance), the distance of the update rule of Sec. 3.4.2.
+# distance), the distance of the update rule of Sec. 3.4.3.
 # ---------------------------------------------------------------------------
 
 def test_sqrt_rn_exact_is_round_to_nearest(oracle_lib):
