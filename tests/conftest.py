@@ -17,3 +17,12 @@ def oracle_lib():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _librfps_built():
+    """Builds librfps.so once if it is missing (a fresh checkout); an existing
+    build is used as it is."""
+    from paper_2606_06255_amd import build as hip_build
+    if not os.path.exists(hip_build.LIB):
+        hip_build.build()
