@@ -101,3 +101,35 @@ def test_errors(rf):
     with pytest.raises(rf.RfpsError) as e:
         rf.cpu_fps(Q, 10, 0)
     assert e.value.status == 2
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_configurations(rf, oracle_lib, seed):
+    # seeded clouds of several shapes, sizes, starts, grids, tiles, team sizes
+    # and both distance forms
+    rng = np.random.default_rng(3000 + seed)
+    for case in range(6):
+        n = int(np.exp(rng.uniform(np.log(2), np.log(6000))))
+        kind = int(rng.integers(0, 5))
+        if kind == 0:
+            P = rng.random((n, 3))
+        elif kind == 1:
+            P = rng.integers(-10, 11, size=(n, 3)) * 0.1
+        elif kind == 2:
+            base = rng.random((max(1, n // 3), 3))
+            P = base[rng.integers(0, len(base), n)]
+        elif kind == 3:
+            P = np.c_[rng.random((n, 2)), np.zeros(n)]
+        else:
+            P = rng.normal(size=(n, 3)) * 10.0 ** rng.integers(-3, 5)
+        P = np.ascontiguousarray(P.astype(np.float32))
+        m = int(rng.integers(1, n + 1))
+        start = int(rng.integers(0, n))
+        euclid = bool(rng.integers(0, 3) == 0)
+        n_vox = int(rng.choice([0, 1, 3, 24, 200]))
+        tile = int(rng.choice([0, 1, 5, 64]))
+        threads = int(rng.choice([1, 2, 3, 8]))
+        ref = oracle_lib.fps(P, m, start, euclid=euclid)
+        got = rf.cpu_fps(P, m, start, n_vox=n_vox, tile=tile, threads=threads, flags=rf.F_SQRT if euclid else 0)
+        same(got, ref, "seed %d case %d kind %d n %d m %d n_vox %d tile %d threads %d euclid %s" % (
+            seed, case, kind, n, m, n_vox, tile, threads, euclid))
