@@ -204,7 +204,7 @@ struct CloudJob {
 // Samples one cloud.  Every thread of every workgroup of the team calls it.
 // `epoch` is the team's exchange counter: it only grows, so slots never need
 // clearing between clouds.  Returns false when an exchange failed (abort).
-template <int R, Scope S, bool E>
+template <int R, Scope S, bool E, bool T>
 __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, int G, unsigned long long *board,
                              uint32_t &epoch, unsigned char *smem, RoundShared &sh, RoundTele &tl,
                              bool record_trace, bool clocks)
@@ -218,8 +218,12 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
     const int ntl = (span > (uint32_t)rank) ? (int)((span - 1 - rank) / G) + 1 : 0;
     const bool use_skip = !(a.flags & RFPS_F_NO_POINT_SKIP);
     constexpr bool euclid = E;  // Euclidean distances (RFPS_F_SQRT), a separate instantiation
-    const bool tele = (a.flags & RFPS_F_TELEMETRY) != 0;
-    const bool trace = record_trace && tid == 0;
+    // counters, phase clocks and the exchange trace exist only in the
+    // instrumented instantiation (T): the default kernels carry none of
+    // their code
+    const bool tele = T && (a.flags & RFPS_F_TELEMETRY) != 0;
+    const bool trace = T && record_trace && tid == 0;
+    clocks = T && clocks;
 
     // ---- LDS layout (the plan checked that it fits) ----
     unsigned long long *tkey = reinterpret_cast<unsigned long long *>(smem);
@@ -1122,7 +1126,7 @@ __device__ void flush_telemetry(IndexHeader *hdr, const RoundTele &tl, bool cloc
 // ---------------------------------------------------------------------------
 // Single cloud: one team made of the whole grid, agent-scope exchange.
 // ---------------------------------------------------------------------------
-template <int R, bool E>
+template <int R, bool E, bool T>
 __device__ __forceinline__ void rounds_single(const RoundArgs &a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1135,7 +1139,7 @@ __device__ __forceinline__ void rounds_single(const RoundArgs &a)
     __syncthreads();
     if (s_status)
         return;
-    const bool tele = (a.flags & RFPS_F_TELEMETRY) != 0;
+    const bool tele = T && (a.flags & RFPS_F_TELEMETRY) != 0;
     const bool clocks = tele && blockIdx.x == 0 && tid == 0;
     CloudJob job;
     job.tb = 0;
@@ -1147,7 +1151,7 @@ __device__ __forceinline__ void rounds_single(const RoundArgs &a)
     job.out_d2 = a.out_d2;
     uint32_t epoch = 0;
     RoundTele tl;
-    const bool ok = sample_cloud<R, Scope::Agent, E>(a, job, blockIdx.x, a.G, a.board, epoch, smem, sh, tl,
+    const bool ok = sample_cloud<R, Scope::Agent, E, T>(a, job, blockIdx.x, a.G, a.board, epoch, smem, sh, tl,
                                                   (a.flags & RFPS_F_TRACE) != 0 && blockIdx.x == 0, clocks);
     if (tele && ok) {
         flush_telemetry(hdr, tl, clocks);
@@ -1162,26 +1166,25 @@ __device__ __forceinline__ void rounds_single(const RoundArgs &a)
 }
 
 // Squared distances (the default) and Euclidean distances are separate
-// kernels, so the default one carries no code of the other form.
-template <int R>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rfps_rounds(RoundArgs a)
-{
-    rounds_single<R, false>(a);
-}
-template <int R>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rfps_rounds_euclid(RoundArgs a)
-{
-    rounds_single<R, true>(a);
-}
+// kernels, and so are the instrumented ones (RFPS_F_TELEMETRY or
+// RFPS_F_TRACE): the default kernel carries no code of either.  Its machine
+// code is close to the instruction cache's size, and compiling the
+// instrumentation out of it shortens a round measurably.
+#define RFPS_ROUNDS_KERNEL(NAME, BODY, E, T)                                                                 \
+    template <int R>                                                                                          \
+    __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void NAME(RoundArgs a)    \
+    {                                                                                                         \
+        BODY<R, E, T>(a);                                                                                     \
+    }                                                                                                         \
+    template __global__ void NAME<2>(RoundArgs);                                                              \
+    template __global__ void NAME<3>(RoundArgs);                                                              \
+    template __global__ void NAME<4>(RoundArgs);                                                              \
+    template __global__ void NAME<8>(RoundArgs);
+RFPS_ROUNDS_KERNEL(k_rfps_rounds, rounds_single, false, false)
+RFPS_ROUNDS_KERNEL(k_rfps_rounds_euclid, rounds_single, true, false)
+RFPS_ROUNDS_KERNEL(k_rfps_rounds_tele, rounds_single, false, true)
+RFPS_ROUNDS_KERNEL(k_rfps_rounds_euclid_tele, rounds_single, true, true)
 
-template __global__ void k_rfps_rounds<2>(RoundArgs);
-template __global__ void k_rfps_rounds<3>(RoundArgs);
-template __global__ void k_rfps_rounds<4>(RoundArgs);
-template __global__ void k_rfps_rounds<8>(RoundArgs);
-template __global__ void k_rfps_rounds_euclid<2>(RoundArgs);
-template __global__ void k_rfps_rounds_euclid<3>(RoundArgs);
-template __global__ void k_rfps_rounds_euclid<4>(RoundArgs);
-template __global__ void k_rfps_rounds_euclid<8>(RoundArgs);
 
 // ---------------------------------------------------------------------------
 // Batches: teams of T workgroups, all on one XCD (found from the hardware
@@ -1193,7 +1196,7 @@ __device__ __forceinline__ uint32_t xcc_id()
     return __builtin_amdgcn_s_getreg((20) | (0 << 6) | ((16 - 1) << 11)) & 0xffu;
 }
 
-template <int R, bool E>
+template <int R, bool E, bool I>
 __device__ __forceinline__ void rounds_batched(const RoundArgs &a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1235,7 +1238,7 @@ __device__ __forceinline__ void rounds_batched(const RoundArgs &a)
     const int rank = (int)s_xrank % T;
     unsigned long long *board = a.board + (size_t)team * (2 * T + 1) * kMaxSlotWords;
     unsigned long long *ctl = board + (size_t)2 * T * kMaxSlotWords;  // the team's control slot
-    const bool tele = (a.flags & RFPS_F_TELEMETRY) != 0;
+    const bool tele = I && (a.flags & RFPS_F_TELEMETRY) != 0;
     RoundTele tl;
     uint32_t epoch = 0, turn = 0;
     for (;;) {
@@ -1280,7 +1283,7 @@ __device__ __forceinline__ void rounds_batched(const RoundArgs &a)
         job.start = bc.starts ? bc.starts[c] : 0;
         job.out_idx = a.out_idx + bc.out_offsets[c];
         job.out_d2 = a.out_d2 ? a.out_d2 + bc.out_offsets[c] : nullptr;
-        if (!sample_cloud<R, Scope::Xcd, E>(a, job, rank, T, board, epoch, smem, sh, tl, false, false))
+        if (!sample_cloud<R, Scope::Xcd, E, I>(a, job, rank, T, board, epoch, smem, sh, tl, false, false))
             return;
     }
     if (tele) {
@@ -1290,39 +1293,30 @@ __device__ __forceinline__ void rounds_batched(const RoundArgs &a)
     }
 }
 
-template <int R>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rfps_rounds_batched(RoundArgs a)
-{
-    rounds_batched<R, false>(a);
-}
-template <int R>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void
-k_rfps_rounds_batched_euclid(RoundArgs a)
-{
-    rounds_batched<R, true>(a);
-}
-
-template __global__ void k_rfps_rounds_batched<2>(RoundArgs);
-template __global__ void k_rfps_rounds_batched<3>(RoundArgs);
-template __global__ void k_rfps_rounds_batched<4>(RoundArgs);
-template __global__ void k_rfps_rounds_batched<8>(RoundArgs);
-template __global__ void k_rfps_rounds_batched_euclid<2>(RoundArgs);
-template __global__ void k_rfps_rounds_batched_euclid<3>(RoundArgs);
-template __global__ void k_rfps_rounds_batched_euclid<4>(RoundArgs);
-template __global__ void k_rfps_rounds_batched_euclid<8>(RoundArgs);
+RFPS_ROUNDS_KERNEL(k_rfps_rounds_batched, rounds_batched, false, false)
+RFPS_ROUNDS_KERNEL(k_rfps_rounds_batched_euclid, rounds_batched, true, false)
+RFPS_ROUNDS_KERNEL(k_rfps_rounds_batched_tele, rounds_batched, false, true)
+RFPS_ROUNDS_KERNEL(k_rfps_rounds_batched_euclid_tele, rounds_batched, true, true)
+#undef RFPS_ROUNDS_KERNEL
 
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
-static const void *rounds_fn(int R, bool batched, bool euclid)
+static const void *rounds_fn(int R, bool batched, bool euclid, bool tele)
 {
 #define RFPS_ROUNDS_FN(K)                                                                                    \
     (R == 2 ? reinterpret_cast<const void *>(K<2>) : R == 3 ? reinterpret_cast<const void *>(K<3>)          \
      : R == 4                                            ? reinterpret_cast<const void *>(K<4>)            \
      : R == 8                                            ? reinterpret_cast<const void *>(K<8>)            \
                                                          : nullptr)
-    if (batched)
+    if (batched) {
+        if (tele)
+            return euclid ? RFPS_ROUNDS_FN(k_rfps_rounds_batched_euclid_tele)
+                          : RFPS_ROUNDS_FN(k_rfps_rounds_batched_tele);
         return euclid ? RFPS_ROUNDS_FN(k_rfps_rounds_batched_euclid) : RFPS_ROUNDS_FN(k_rfps_rounds_batched);
+    }
+    if (tele)
+        return euclid ? RFPS_ROUNDS_FN(k_rfps_rounds_euclid_tele) : RFPS_ROUNDS_FN(k_rfps_rounds_tele);
     return euclid ? RFPS_ROUNDS_FN(k_rfps_rounds_euclid) : RFPS_ROUNDS_FN(k_rfps_rounds);
 #undef RFPS_ROUNDS_FN
 }
@@ -1330,8 +1324,8 @@ static const void *rounds_fn(int R, bool batched, bool euclid)
 size_t rfps_rounds_static_lds(int R)
 {
     size_t mx = 0;
-    for (int b = 0; b < 4; ++b) {
-        const void *fn = rounds_fn(R, (b & 1) != 0, (b & 2) != 0);
+    for (int b = 0; b < 8; ++b) {
+        const void *fn = rounds_fn(R, (b & 1) != 0, (b & 2) != 0, (b & 4) != 0);
         hipFuncAttributes attr;
         if (!fn || hipFuncGetAttributes(&attr, fn) != hipSuccess)
             return 0;
@@ -1380,7 +1374,8 @@ hipError_t launch_rfps_rounds(const IndexView &v, int m, int start, const Sample
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || m <= 1)
         return e;
-    const void *fn = rounds_fn(L.R, false, (L.flags & RFPS_F_SQRT) != 0);
+    const void *fn = rounds_fn(L.R, false, (L.flags & RFPS_F_SQRT) != 0,
+                               (L.flags & (RFPS_F_TELEMETRY | RFPS_F_TRACE)) != 0);
     if (!fn)
         return hipErrorInvalidValue;
     RoundArgs a = round_args(v, m, start, L, out_idx, out_d2);
@@ -1432,7 +1427,8 @@ hipError_t launch_rfps_rounds_batched(const IndexView &v, const SampleLaunch &L,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    const void *fn = rounds_fn(L.R, true, (L.flags & RFPS_F_SQRT) != 0);
+    const void *fn = rounds_fn(L.R, true, (L.flags & RFPS_F_SQRT) != 0,
+                               (L.flags & (RFPS_F_TELEMETRY | RFPS_F_TRACE)) != 0);
     if (!fn)
         return hipErrorInvalidValue;
     RoundArgs a = round_args(v, 0, 0, L, out_idx, out_d2);
