@@ -134,13 +134,20 @@ def sweep_cloud(x: torch.Tensor, m: int, idx=None):
     ms = np.zeros(MLP_CANDIDATES)
     prune = np.zeros(MLP_CANDIDATES)
     for k, (nv, sh) in enumerate(candidates()):
+        # the time is the default (uninstrumented) sampler's; a second,
+        # untimed call with telemetry gives the pruning rate
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
         idx = build_index(x, n_vox=nv, shell=sh, reuse=idx)
-        sample(idx, m, 0, flags=F_TELEMETRY, out_idx=out_i, out_d2=out_d)
+        sample(idx, m, 0, out_idx=out_i, out_d2=out_d)
         b.record(stream)
         torch.cuda.synchronize()
         st = read_status(idx)
+        if st == 0:
+            if not torch.equal(out_i, ref):
+                raise RuntimeError("candidate %d changed the sampled sequence" % k)
+            sample(idx, m, 0, flags=F_TELEMETRY, out_idx=out_i, out_d2=out_d)
+            st = read_status(idx)
         if st == 6:
             # this grid's share per workgroup does not fit on chip: not a choice
             ms[k], prune[k] = np.nan, np.nan
