@@ -179,7 +179,7 @@ rfps_status rfps_build_index(const float *xyz, int32_t n, const rfps_params *par
  *            call in stream order.
  *   m        samples, 1 <= m <= n.
  *   start    index of the first sample (the seed s_0), 0 <= start < n.
- *   params   host, may be NULL; only `groups` and `flags` are read.
+ *   params   host, may be NULL; only `groups`, `lookahead` and `flags` are read.
  *   out_idx  device, int32 [m]: original indices of the samples in order.
  *   out_d2   device, float32 [m] or NULL: out_d2[0] = +inf; out_d2[j] is the
  *            squared distance of sample j to the nearest earlier sample

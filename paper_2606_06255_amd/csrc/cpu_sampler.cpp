@@ -32,6 +32,7 @@
 #include <sched.h>
 
 #include "../../include/rfps.h"
+#include "prune_bound.h"
 
 // The distance must be evaluated as written: no FMA contraction.
 #pragma clang fp contract(off)
@@ -63,27 +64,9 @@ inline float bitsf(uint32_t u)
 
 inline uint64_t pack(float d, uint32_t orig) { return ((uint64_t)fbits(d) << 32) | (uint32_t)~orig; }
 
-// Skip threshold of a tile with radius R and tile distance dv: skipping the
-// tile for sample s is safe when fl32(|s - c|^2) >= thr.  The same bound as
-// the GPU samplers use: |s - c| >= R + sqrt(dv / (1 - 2^-20)) gives every
-// member an FP32 squared distance >= dv (the FP32 formula loses at most a
-// factor (1 - 2^-24)^5), so the strict update cannot fire.  NaN never skips.
-inline float skip_threshold(float R, float dv)
-{
-    if (dv == 0.0f)
-        return 0.0f;
-    if (!(dv >= 0x1p-100f) || !(dv <= 0x1p100f))
-        return std::nanf("");
-    double q = (double)R + std::sqrt((double)dv * (1.0 + 0x1p-19));
-    q *= 1.0 + 0x1p-50;
-    const double t64 = q * q * (1.0 + 0x1p-50) * (1.0 + 0x1p-20);
-    if (!(t64 <= 3.0e38))
-        return std::nanf("");
-    float thr = (float)t64;
-    if ((double)thr < t64)
-        thr = std::nextafter(thr, INFINITY);
-    return thr;
-}
+// Skip threshold of a tile with radius R and tile distance dv: the bound
+// the GPU samplers use, from the one definition in prune_bound.h.
+using rfps::prune_threshold;
 
 // Euclidean mode: the largest FP32 value whose rounded root equals that of
 // x (IEEE sqrtf rounds correctly); min and arg max over these class tops
@@ -347,7 +330,7 @@ void run_member(Team &tm, int r)
                 uint64_t k = sh.key[l];
                 if (update_tile(I, pd, sh.tile[l], sx, sy, sz, tm.euclid, k)) {
                     sh.key[l] = k;
-                    sh.thr[l] = skip_threshold(sh.rad[l], bitsf((uint32_t)(k >> 32)));
+                    sh.thr[l] = prune_threshold(sh.rad[l], bitsf((uint32_t)(k >> 32)));
                 }
             }
             local = std::max(local, sh.key[l]);
@@ -437,7 +420,7 @@ rfps_status cpu_sample(const float *xyz, int32_t n, int32_t m, int32_t start, co
         sh.cy.push_back(I.cy[t]);
         sh.cz.push_back(I.cz[t]);
         sh.rad.push_back(I.rad[t]);
-        sh.thr.push_back(skip_threshold(I.rad[t], dmax));
+        sh.thr.push_back(prune_threshold(I.rad[t], dmax));
         sh.key.push_back(pack(dmax, best));
     }
     out_idx[0] = start;

@@ -104,6 +104,9 @@ static int run_batch(int argc, char **argv)
     const rfps_status st = rfps_batched_read_status(ws, ws_bytes, s);
     printf("batch=%d n=%d m_total=%d steps=%d RadiusFPS-G batched: %.3f ms per batch, status=%s\n", batch, n,
            m_total, steps, steps > 0 ? ms / steps : 0.0f, rfps_status_str(st));
+    fflush(stdout);
+    hipEventDestroy(a);
+    hipEventDestroy(b);
     hipFree(ws);
     hipFree(d2);
     hipFree(idx);
@@ -116,9 +119,9 @@ static int run_batch(int argc, char **argv)
 
 int main(int argc, char **argv)
 {
-    // line-buffered, so that the result lines are written even when a
-    // profiler attached to the process fails while the process exits
-    setvbuf(stdout, nullptr, _IOLBF, 0);
+    // every HIP object this driver creates (events, stream, buffers) is
+    // released before main returns, so none is left for the runtime's
+    // teardown after an attached profiler has finalised
     if (argc > 1 && strcmp(argv[1], "--batch") == 0)
         return run_batch(argc, argv);
     if (argc < 3) {
@@ -203,6 +206,9 @@ int main(int argc, char **argv)
            plain >= 0 ? (plain ? "plain one-workgroup" : "plain persistent") : "RadiusFPS-G",
            steps > 0 ? ms / steps : 0.0f, rfps_status_str(st), m > 1 ? out[1] : -1, m > 2 ? out[2] : -1,
            m > 3 ? out[3] : -1);
+    fflush(stdout);
+    hipEventDestroy(a);
+    hipEventDestroy(b);
     hipFree(ws);
     hipFree(d2);
     hipFree(idx);

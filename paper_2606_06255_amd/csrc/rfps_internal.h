@@ -8,6 +8,7 @@
 #include <stdint.h>
 
 #include "../../include/rfps.h"
+#include "prune_bound.h"
 
 // The distance must be evaluated as written: no FMA contraction anywhere.
 #pragma clang fp contract(off)
@@ -317,38 +318,8 @@ __device__ __forceinline__ void set_status(uint32_t *word, uint32_t code)
                                          __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Pruning threshold of a tile with radius R (rounded up) and Dist_v = dv.
-//
-// Skipping the tile for sample s is safe when the FP32 value
-// q = fl32(||s - c||^2), computed with the same formula as a point distance,
-// satisfies q >= thr.  Derivation: q <= (1 + 2^-24)^5 ||s - c||^2, so
-// q >= thr implies ||s - c|| >= R + sqrt(dv / (1 - 2^-20)); by the triangle
-// inequality (eq. triangle_inequality_bound) every member p then has
-// ||p - s||^2 >= dv / (1 - 2^-20), and its FP32 squared distance, at least
-// (1 - 2^-24)^5 ||p - s||^2, is >= dv >= Dist_p[p]: the strict update cannot
-// fire (eq. radius_pruning_correctness).  The FP64 steps below are rounded
-// up by relative margins far above their rounding error.  dv == 0 means
-// nothing can decrease (thr = 0 always skips); dv below 2^-100 or above
-// 2^100 returns NaN, which never skips.
-__device__ __forceinline__ float prune_threshold(float R, float dv)
-{
-    if (dv == 0.0f)
-        return 0.0f;
-    if (!(dv >= 0x1p-100f) || !(dv <= 0x1p100f))
-        return __uint_as_float(0x7fc00000u);
-    // dv * (1 + 2^-19) >= dv / (1 - 2^-20); the product's rounding is covered
-    // by the 2^-50 factors below, like the square root's and the sum's
-    double q = (double)R + sqrt((double)dv * (1.0 + 0x1p-19));
-    q *= 1.0 + 0x1p-50;
-    double T = q * q * (1.0 + 0x1p-50);
-    double t64 = T * (1.0 + 0x1p-20);
-    if (!(t64 <= 3.0e38))
-        return __uint_as_float(0x7fc00000u);
-    float thr = (float)t64;
-    if ((double)thr < t64)
-        thr = nextafterf(thr, INFINITY);
-    return thr;
-}
+// The pruning threshold of a tile, prune_threshold(R, dv), is defined in
+// prune_bound.h, which the CPU sampler shares.
 
 // ---------------------------------------------------------------------------
 // Exchange board of the persistent kernels.

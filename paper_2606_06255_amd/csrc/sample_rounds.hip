@@ -1214,9 +1214,11 @@ __device__ __forceinline__ void rounds_batched(const RoundArgs &a)
             const uint32_t x = xcc_id();
             s_xcc = x;
             s_xrank = x < kMaxXcds ? atomicAdd(&st->xcd_count[x], 1u) : 0xffffffffu;
-            atomicAdd(&st->joined, 1u);
+            // release / acquire: a workgroup that sees every join also sees
+            // every XCD count bumped before it
+            __hip_atomic_fetch_add(&st->joined, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             uint32_t spin = 0;
-            while (__hip_atomic_load(&st->joined, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x &&
+            while (__hip_atomic_load(&st->joined, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x &&
                    ++spin < kSpinLimit) {
             }
             if (spin >= kSpinLimit || x >= kMaxXcds) {

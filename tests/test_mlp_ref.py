@@ -1,6 +1,8 @@
 """Pins of the FP64 reference of the voxel-parameter network (oracle/mlp_ref.py):
 finite differences, closed forms and brute force, none of which reuse the
 reference's own formulas."""
+import os
+
 import numpy as np
 import pytest
 
@@ -148,3 +150,60 @@ def test_candidates():
     assert R.N_CAND == 36 and R.OUT == 72 and R.N_PARAMS == 41928
     assert R.candidate(0) == (12, 0.0) and R.candidate(35) == (192, 20.0)
     assert len({R.candidate(k) for k in range(R.N_CAND)}) == 36
+
+
+# ---------------------------------------------------------------------------
+# The forward pass against a network worked out by hand
+# (tests/golden/mlp_forward_tiny.txt): power-of-two weights, negative
+# pre-activations at both hidden layers, every output exact in FP64.
+# ---------------------------------------------------------------------------
+GOLDEN_MLP = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "mlp_forward_tiny.txt")
+
+
+def _golden_network():
+    P = {name: np.zeros(shape) for name, shape in R.SHAPES}
+    X = np.zeros((2, R.F_IN), dtype=np.float32)
+    Y = None
+    rows = []
+    for line in open(GOLDEN_MLP):
+        line = line.split("#")[0].split()
+        if not line:
+            continue
+        tag, rest = line[0], line[1:]
+        if tag in ("W1", "W2", "W3"):
+            P[tag][int(rest[0]), int(rest[1])] = float(rest[2])
+        elif tag in ("b1", "b2", "b3"):
+            P[tag][int(rest[0])] = float(rest[1])
+        elif tag == "X":
+            X[int(rest[0]), int(rest[1])] = float(rest[2])
+        elif tag == "Y":
+            rows.append((int(rest[0]), int(rest[1]), float(rest[2])))
+    Y = np.tile(P["b3"], (2, 1))
+    for b, k, v in rows:
+        Y[b, k] = v
+    theta = np.concatenate([P[name].ravel() for name, _ in R.SHAPES])
+    return theta, X, Y, P
+
+
+def test_forward_matches_hand_derived_network():
+    theta, X, Y, _ = _golden_network()
+    for quantize in (True, False):
+        out, _ = R.forward(theta, X, quantize=quantize)
+        assert np.array_equal(out, Y)
+
+
+def test_hand_derived_network_separates_relu_mistakes():
+    """The fixture is sharp enough: a forward pass without either hidden
+    ReLU, or with one on the output, disagrees with it."""
+    theta, X, Y, P = _golden_network()
+    Xd = X.astype(np.float64)
+
+    def fwd(relu1, relu2, relu_out):
+        act = lambda z, on: np.maximum(z, 0.0) if on else z  # noqa: E731
+        a1 = act(Xd @ P["W1"].T + P["b1"], relu1)
+        a2 = act(a1 @ P["W2"].T + P["b2"], relu2)
+        return act(a2 @ P["W3"].T + P["b3"], relu_out)
+
+    assert np.array_equal(fwd(True, True, False), Y)
+    for variant in ((False, True, False), (True, False, False), (True, True, True)):
+        assert not np.array_equal(fwd(*variant), Y)
