@@ -49,7 +49,8 @@ typedef enum rfps_status {
     RFPS_ERR_UNSUPPORTED = 5, /* no usable gfx950 device, or a launch shape it cannot run */
     RFPS_ERR_CAPACITY = 6,    /* the cloud's share per workgroup exceeds the on-chip budget */
     RFPS_ERR_TIMEOUT = 7,     /* a bounded wait inside a persistent kernel expired */
-    RFPS_ERR_INTERNAL = 8     /* an internal consistency check of a kernel failed */
+    RFPS_ERR_INTERNAL = 8,    /* an internal consistency check of a kernel failed */
+    RFPS_ERR_SCRATCH_LIMIT = 9 /* input too large for the fixed array of rfps_sample_batched_noalloc */
 } rfps_status;
 
 /* rfps_params.flags */
@@ -286,6 +287,31 @@ rfps_status rfps_sample_batched(const float *xyz, int32_t n, const int32_t *offs
                                 const int32_t *m, const int32_t *starts, int32_t batch,
                                 int32_t m_total, const rfps_params *params, void *ws,
                                 size_t ws_bytes, int32_t *out_idx, float *out_d2, void *stream);
+
+/*
+ * rfps_sample_batched without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops and
+ * harnesses that forbid hipMalloc).  Same method, arguments (minus ws and
+ * ws_bytes), outputs and device-side error behaviour (outputs -1 / NaN) as
+ * rfps_sample_batched.  The workspace is a fixed array inside the library,
+ * rfps_noalloc_scratch_bytes() = 128 MiB per device, created when the
+ * library's device code is loaded on that device and held until the process
+ * ends; the call allocates nothing (no hipMalloc, no allocating library call).
+ *   Limit: rfps_batched_workspace_size(n, batch, params) must not exceed that
+ *   size (RFPS_ERR_SCRATCH_LIMIT otherwise, with nothing enqueued); about
+ *   1.7 M points in 32 clouds.
+ *   Sharing: every call on one device uses that device's one array, and the
+ *   array keeps the last call's contents (each call clears what must start at
+ *   zero itself).  Calls in one stream order are safe; calls that overlap on
+ *   one GPU (two streams or threads at once) race and give undefined
+ *   results.  The device-side status word stays in the array and has no
+ *   reader: check the outputs for -1 / NaN.
+ */
+size_t rfps_noalloc_scratch_bytes(void);
+rfps_status rfps_sample_batched_noalloc(const float *xyz, int32_t n, const int32_t *offsets,
+                                        const int32_t *m, const int32_t *starts, int32_t batch,
+                                        int32_t m_total, const rfps_params *params, int32_t *out_idx,
+                                        float *out_d2, void *stream);
 
 /* Waits for the stream and returns the device-side status the last batched
  * call recorded in ws (RFPS_OK if none). */

@@ -20,7 +20,7 @@ RFPS_OK = 0
 STATUS_NAMES = {
     0: "RFPS_OK", 1: "RFPS_ERR_INVALID_ARG", 2: "RFPS_ERR_NONFINITE", 3: "RFPS_ERR_WORKSPACE",
     4: "RFPS_ERR_DEVICE", 5: "RFPS_ERR_UNSUPPORTED", 6: "RFPS_ERR_CAPACITY", 7: "RFPS_ERR_TIMEOUT",
-    8: "RFPS_ERR_INTERNAL",
+    8: "RFPS_ERR_INTERNAL", 9: "RFPS_ERR_SCRATCH_LIMIT",
 }
 F_NO_PRUNE = 0x01
 F_NO_POINT_SKIP = 0x02
@@ -103,6 +103,10 @@ def lib() -> ctypes.CDLL:
         L.rfps_batched_workspace_size.restype = sz
         L.rfps_sample_batched.argtypes = [vp, i32, vp, vp, vp, i32, i32, P(rfps_params), vp, sz, vp, vp, vp]
         L.rfps_sample_batched.restype = ctypes.c_int
+        L.rfps_sample_batched_noalloc.argtypes = [vp, i32, vp, vp, vp, i32, i32, P(rfps_params), vp, vp, vp]
+        L.rfps_sample_batched_noalloc.restype = ctypes.c_int
+        L.rfps_noalloc_scratch_bytes.argtypes = []
+        L.rfps_noalloc_scratch_bytes.restype = sz
         L.rfps_batched_read_status.argtypes = [vp, sz, vp]
         L.rfps_batched_read_status.restype = ctypes.c_int
         L.rfps_batched_read_telemetry.argtypes = [vp, sz, vp, P(rfps_telemetry)]
@@ -403,6 +407,35 @@ def sample_batched(xyz: torch.Tensor, offsets, m, starts=None, m_total: int | No
     if check:
         _check(lib().rfps_batched_read_status(ws.ptr, ws.nbytes, _stream(dev)), "device status")
     return out_idx, out_d2
+
+
+def sample_batched_noalloc(xyz: torch.Tensor, offsets: torch.Tensor, m: torch.Tensor, m_total: int,
+                           out_idx: torch.Tensor, out_d2: torch.Tensor, starts: torch.Tensor | None = None,
+                           n_vox: int = 0, tile: int = 0, groups: int = 0, lookahead: int = 0, flags: int = 0,
+                           shell: float = 0.0):
+    """rfps_sample_batched_noalloc on torch's current stream: the batched call
+    with the library's fixed scratch array as its workspace.  Every tensor
+    (offsets, m, starts, outputs) must already be on the device: nothing is
+    allocated and nothing waits for the device."""
+    _check_xyz(xyz)
+    dev = xyz.device
+    for name, t, dt in (("offsets", offsets, torch.int32), ("m", m, torch.int32), ("out_idx", out_idx, torch.int32),
+                        ("out_d2", out_d2, torch.float32), ("starts", starts, torch.int32)):
+        if t is None and name == "starts":
+            continue
+        if not (isinstance(t, torch.Tensor) and t.device == dev and t.dtype == dt and t.is_contiguous()):
+            raise ValueError("%s must be a contiguous %s tensor on %s" % (name, dt, dev))
+    batch = offsets.numel() - 1
+    p = _params(n_vox, tile, groups, flags, lookahead, shell)
+    _check(lib().rfps_sample_batched_noalloc(xyz.data_ptr(), xyz.shape[0], offsets.data_ptr(), m.data_ptr(),
+                                             0 if starts is None else starts.data_ptr(), batch, int(m_total),
+                                             ctypes.byref(p), out_idx.data_ptr(), out_d2.data_ptr(), _stream(dev)),
+           "rfps_sample_batched_noalloc")
+    return out_idx, out_d2
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().rfps_noalloc_scratch_bytes())
 
 
 def batched_read_status(ws: BatchWorkspace) -> int:

@@ -268,6 +268,7 @@ const char *rfps_status_str(rfps_status s)
     case RFPS_ERR_CAPACITY: return "cloud share per workgroup exceeds the on-chip budget";
     case RFPS_ERR_TIMEOUT: return "bounded wait in a persistent kernel expired";
     case RFPS_ERR_INTERNAL: return "internal consistency check failed";
+    case RFPS_ERR_SCRATCH_LIMIT: return "input exceeds the library's fixed scratch array (no-allocation entry point)";
     }
     return "unknown status";
 }
@@ -570,6 +571,58 @@ rfps_status rfps_sample_batched(const float *xyz, int32_t n, const int32_t *offs
     if (e == hipErrorCooperativeLaunchTooLarge)
         return RFPS_ERR_UNSUPPORTED;
     return e == hipSuccess ? RFPS_OK : RFPS_ERR_DEVICE;
+}
+
+// ---------------------------------------------------------------------------
+// No-allocation form of the batched call: its workspace is a fixed device
+// array of this file instead of a caller's buffer.  In host code `scratch`
+// names a host-side stand-in, never the device memory: the device address is
+// resolved once per device with hipGetSymbolAddress (with that device
+// current) and only that address is handed to the kernels.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64];
+bool g_scratch_done[64];
+hipError_t g_scratch_err[64];
+}  // namespace
+
+// Device address of this device's copy of `scratch` (nullptr on failure).
+static void *noalloc_scratch()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[dev]) {
+        void *ptr = nullptr;
+        g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? ptr : nullptr;
+        g_scratch_done[dev] = true;
+    }
+    return g_scratch_ptr[dev];
+}
+
+size_t rfps_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
+
+rfps_status rfps_sample_batched_noalloc(const float *xyz, int32_t n, const int32_t *offsets, const int32_t *m,
+                                        const int32_t *starts, int32_t batch, int32_t m_total,
+                                        const rfps_params *params, int32_t *out_idx, float *out_d2, void *stream)
+{
+    if (!xyz || !offsets || !m || !out_idx || n < 1 || n > kMaxPoints || batch < 1 || batch > kMaxBatch ||
+        batch > n || m_total < batch || m_total > n || !params_valid(params))
+        return RFPS_ERR_INVALID_ARG;
+    const size_t need = layout_batch(n, batch, params ? params->n_vox : 0, use_shells(params)).total;
+    if (need > kNoAllocScratchBytes)
+        return RFPS_ERR_SCRATCH_LIMIT;
+    void *ws = noalloc_scratch();
+    if (!ws)
+        return RFPS_ERR_DEVICE;
+    return rfps_sample_batched(xyz, n, offsets, m, starts, batch, m_total, params, ws, need, out_idx, out_d2,
+                               stream);
 }
 
 static rfps_status read_header(const void *ws, size_t ws_bytes, void *stream, IndexHeader *h)

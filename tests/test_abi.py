@@ -35,11 +35,12 @@ def test_every_declared_symbol_is_exported(L):
 
 def test_status_strings(L):
     import paper_2606_06255_amd as rf
-    for code in range(8):
+    for code in range(10):
         s = L.rfps_status_str(code)
         assert isinstance(s, bytes) and len(s) > 0
     assert L.rfps_status_str(99) == b"unknown status"
     assert rf.STATUS_NAMES[7] == "RFPS_ERR_TIMEOUT"
+    assert rf.STATUS_NAMES[9] == "RFPS_ERR_SCRATCH_LIMIT"
 
 
 def test_workspace_sizes(L):
@@ -206,3 +207,29 @@ def test_mlp_host_checks(L):
     assert L.rfps_mlp_features(fake, 0, fake, big, fake, None) == 1
     assert L.rfps_mlp_load(fake, big, None, None) == 1
     assert L.rfps_mlp_save(None, big, fake, None) == 3
+
+
+def test_noalloc_host_checks(L):
+    """rfps_sample_batched_noalloc rejects bad arguments and inputs beyond its
+    fixed array on the host, before any device work."""
+    import paper_2606_06255_amd as rf
+    cap = L.rfps_noalloc_scratch_bytes()
+    assert cap == 128 << 20
+    fake = ctypes.c_void_p(0x1000)
+    out = ctypes.c_void_p(0x2000)
+
+    def call(xyz=fake, n=100, off=fake, m=fake, b=4, mt=20, p=None, oi=out):
+        return L.rfps_sample_batched_noalloc(xyz, n, off, m, None, b, mt, p, oi, None, None)
+    assert call(xyz=None) == 1
+    assert call(off=None) == 1
+    assert call(oi=None) == 1
+    assert call(b=0) == 1
+    assert call(mt=3) == 1
+    assert call(n=0) == 1
+    assert call(p=ctypes.byref(rf.rfps_params(lookahead=5))) == 1
+    # the largest batch that fits and the first that does not
+    assert 0 < L.rfps_batched_workspace_size(1_500_000, 32, None) <= cap
+    big = 1 << 26
+    assert L.rfps_batched_workspace_size(big, 1, None) > cap
+    assert call(n=big, b=1, mt=1) == 9
+    assert call(n=big, b=32, mt=64) == 9
