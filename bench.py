@@ -33,6 +33,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ms per cloud & selected pts/s, RadiusFPS-G vs plain FPS, bit-exact indices"
 HBM_PEAK_GBS = 8000.0
+# LDS: 256 compute units x 128 bytes per clock x 2.4 GHz (the per-CU LDS rate
+# of CDNA3, taken as the floor for gfx950)
+LDS_PEAK_GBS = 256 * 128 * 2.4
+PHASES = ("lookahead", "lookahead_copy", "lookahead_select", "exchange", "exchange_poll", "exchange_keys",
+          "wait", "merge", "merge_list", "merge_rank", "merge_walk", "merge_picks", "apply", "apply_loop")
 WORKLOADS = {
     "dense_lidar": "dense LiDAR-like cloud, 128 beams x 8192 azimuth, N=1,048,576, M=65,536",
     "room": "indoor room-like cloud, N=80,000, M=20,000",
@@ -203,6 +208,23 @@ def main():
               out_idx=out_i, out_d2=out_d)
     tel = rf.read_telemetry(idx)
     tr, hz = rf.read_trace(idx)
+    lookahead = args.lookahead or 2
+    # phase clocks of workgroup 0 without the counters (instrumented kernel)
+    idx = rf.build_index(x, n_vox=n_vox, reuse=idx)
+    rf.sample(idx, M, 0, groups=args.groups, lookahead=args.lookahead, flags=rf.F_CLOCKS | fdist, out_idx=out_i,
+              out_d2=out_d)
+    clk = rf.read_telemetry(idx)
+    nr = max(1, clk["exchanges"])
+    phases = {k: clk["ticks_" + k] / clk["tick_hz"] / nr * 1e6 for k in PHASES}
+    phases["lookahead_update"] = phases["lookahead"] - phases["lookahead_copy"] - phases["lookahead_select"]
+    phases["round"] = sum(phases[k] for k in ("lookahead", "exchange", "merge", "apply"))
+    merge_stats = {"above": clk["merge_above"] / nr, "listed": clk["merge_listed"] / nr,
+                   "failures": clk["merge_failures"] / nr}
+    # latency floor of one exchange round: bare exchanges of the sampler's
+    # slot size among the same workgroups (nothing else in the round)
+    G_used = args.groups or 0
+    ex_floor_us = rf.probe_exchange(idx, words=6 * lookahead + 2, rounds=2000, groups=G_used)
+    ex_floor_1w_us = rf.probe_exchange(idx, words=1, rounds=2000, groups=G_used)
     # per exchange round: (publish time, outcome time | picks << 48)
     picks_per_round = (tr[:, 1] >> np.uint64(48)).astype(np.int64)
     t_done = (tr[:, 1] & np.uint64((1 << 48) - 1)).astype(np.int64)
@@ -221,6 +243,12 @@ def main():
     digest = source_digest()
     traffic = None if euclid else stored_traffic(args.workload, digest)
     pruned_frac = 1.0 - tel["points_visited"] / max(1, tel["iters"] * N)
+    rounds = int(len(tr))
+    lat_floor_ms = rounds * ex_floor_us / 1e3
+    fr = {"hbm_algorithmic": achieved / HBM_PEAK_GBS, "lds": achieved / LDS_PEAK_GBS,
+          "latency": lat_floor_ms / (samp_s * 1e3)}
+    if traffic is not None:
+        fr["hbm_counted"] = traffic / samp_s / 1e9 / HBM_PEAK_GBS
 
     result = {
         "metric": METRIC,
@@ -248,17 +276,29 @@ def main():
         "index": {"voxels": info["n_voxels"], "tiles": NT},
         "pruning": {"point_visit_fraction": 1.0 - pruned_frac, "pruned_fraction": pruned_frac,
                     "tiles_pruned_fraction": tel["tiles_pruned"] / max(1, tel["tile_tests"]), **tel},
-        "exchange_rounds": int(len(tr)),
+        "exchange_rounds": rounds,
         "selections_per_round": float((M - 1) / max(1, len(tr))),
         "exchange_us": {"p10": float(np.percentile(ex_us, 10)), "p50": float(np.percentile(ex_us, 50)),
                         "p90": float(np.percentile(ex_us, 90)), "round_p50": float(np.median(it_us)),
                         "note": "publish to merged outcome of workgroup 0, per exchange round"},
-        "latency_floor_ms": float(np.median(ex_us)) * len(tr) / 1e3,
-        "roofline": {"bound": "hbm", "kernel": "k_rfps_rounds%s<%d>" % ("_euclid" if euclid else "",
-                                                                           args.lookahead or 2),
+        "round_phases_us": phases,
+        "merge_per_round": merge_stats,
+        "exchange_floor_us": {"slot_words": 6 * lookahead + 2, "per_round": ex_floor_us,
+                              "one_word_per_round": ex_floor_1w_us,
+                              "note": "bare exchange rounds (publish, read every slot) among the same workgroups"},
+        "latency_floor_ms": lat_floor_ms,
+        # the sampler keeps its state in LDS and waits on one exchange per
+        # round: it is latency-bound.  achieved / peak / frac are the
+        # algorithmic bytes of a launch over its time against the HBM peak;
+        # `fractions` sets them beside the LDS peak, the counted HBM bytes and
+        # the exchange latency floor (rounds x bare exchange round), and
+        # `bound` names the largest of them.
+        "roofline": {"bound": max(fr, key=fr.get).split("_")[0], "kernel":
+                     "k_rfps_rounds%s<%d>" % ("_euclid" if euclid else "", lookahead),
                      "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "alg_bytes_per_launch": alg_bytes,
+                     "traffic": traffic, "fractions": fr, "lds_peak_gbs": LDS_PEAK_GBS,
+                     "alg_bytes_per_launch": alg_bytes,
                      "alg_bytes_per_selection": alg_bytes / max(1, M - 1), "source_digest": digest},
     }
 
@@ -719,9 +759,15 @@ def run_batch(args, rf, dev, stream):
         "ms_per_cloud": ms_per_step / B,
         "autotune": {"chosen": chosen, "median_ms": tuned_ms, "seconds": tune_s},
         "pruning": {"point_visit_fraction": visit, **tel},
-        "roofline": {"bound": "hbm", "kernel": "whole batched call (index build + k_rfps_rounds_batched)",
+        # as for one cloud: every team waits on one XCD-local exchange per
+        # round, so the call is latency-bound; the byte fractions stand beside
+        # it (no bare-exchange floor is measured for teams)
+        "roofline": {"bound": "latency", "kernel": "whole batched call (index build + k_rfps_rounds_batched)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "alg_bytes_per_launch": alg_bytes},
+                     "traffic": None, "fractions": {"hbm_algorithmic": achieved / HBM_PEAK_GBS,
+                                                    "lds": achieved / LDS_PEAK_GBS},
+                     "lds_peak_gbs": LDS_PEAK_GBS, "exchange_rounds": tel["exchanges"],
+                     "alg_bytes_per_launch": alg_bytes},
         "comparators": comps,
         "speedup_vs_per_cloud_rfps": comps["per_cloud_rfps_ms"] / ms_per_step,
         "speedup_vs_per_cloud_plain_persistent": comps["per_cloud_plain_persistent_ms"] / ms_per_step,

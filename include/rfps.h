@@ -72,6 +72,10 @@ typedef enum rfps_status {
  * output; NO_PRUNE, NO_POINT_SKIP and SQRT apply, TELEMETRY and TRACE are
  * not available with it (RFPS_ERR_UNSUPPORTED). */
 #define RFPS_F_UNFUSED 0x40u
+/* Phase clocks of workgroup 0 of the multi-pick sampler (rfps_sample only),
+ * read by rfps_read_telemetry: the instrumented kernel runs with its counters
+ * off, so that the clocks see no counting work.  Same output. */
+#define RFPS_F_CLOCKS 0x80u
 
 typedef struct rfps_params {
     /* Voxel bins per axis, n_vox of eq. voxel_size (Sec. 3.2); 1..1024.
@@ -133,6 +137,30 @@ typedef struct rfps_telemetry {
      * yet published at the first pass (waiting for the slowest workgroup) */
     int64_t ticks_wait;
     int64_t reserved;
+    /* finer clocks of workgroup 0 (multi-pick sampler, single cloud): the
+     * merge's listing (key compaction and any cut of a long list), its
+     * ranking pass, its certification walk and its hand-over of the picks;
+     * the lookahead's copy of the tile state and its steps; the exchange's
+     * polling and its forming of the candidate keys */
+    int64_t ticks_merge_list;
+    int64_t ticks_merge_rank;
+    int64_t ticks_merge_walk;
+    int64_t ticks_merge_picks;
+    int64_t ticks_lookahead_copy;
+    int64_t ticks_lookahead_steps;
+    int64_t ticks_exchange_poll;
+    int64_t ticks_exchange_keys;
+    /* per-round merge statistics summed over the rounds: candidates above
+     * the largest bound, candidates listed, failed certifications */
+    int64_t merge_above;
+    int64_t merge_listed;
+    int64_t merge_failures;
+    /* workgroup 0's own share of the apply phase (its tile loop, without
+     * waiting for the other wavefronts) and of the lookahead (choosing each
+     * local candidate and its runner-up, without the local updates) */
+    int64_t ticks_apply_loop;
+    int64_t ticks_lookahead_select;
+    int64_t reserved2[3];
 } rfps_telemetry;
 
 /* Shape of a built index, read back by rfps_read_index_info(). */
@@ -224,6 +252,20 @@ rfps_status rfps_read_telemetry(const rfps_index *index, void *stream, rfps_tele
  * of out[2k+1] hold the number of selections the round settled (mask them
  * off before using the time).  *ticks_per_s receives the clock's rate.
  * Returns the number of pairs. */
+/*
+ * Latency floor of the sampler's exchange (measurement only): `groups`
+ * workgroups (0 = one per compute unit, at most 256) run `rounds` exchanges
+ * of `words` (1..16) epoch-tagged 64-bit words each per workgroup, with
+ * nothing else in a round, through the same agent-scope stores, loads and
+ * polling as the multi-pick sampler (which publishes 6 * lookahead + 2
+ * words).  Uses the index's exchange board and trace buffer as scratch (the
+ * next sampling call clears the board; the last trace is overwritten).
+ * Waits for the stream.  *us_per_round receives the wall-clock time per
+ * exchange of workgroup 0.  RFPS_ERR_TIMEOUT if a bounded wait expired.
+ */
+rfps_status rfps_probe_exchange(const rfps_index *index, int32_t groups, int32_t words, int32_t rounds,
+                                void *stream, double *us_per_round);
+
 int32_t rfps_read_trace(const rfps_index *index, void *stream, uint64_t *out, int32_t cap,
                         double *ticks_per_s);
 

@@ -29,6 +29,7 @@ F_TRACE = 0x08
 F_SINGLE_PICK = 0x10
 F_SQRT = 0x20
 F_UNFUSED = 0x40
+F_CLOCKS = 0x80
 WS_ALIGN = 256
 
 
@@ -46,7 +47,11 @@ class rfps_telemetry(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "iters", "tiles", "tile_tests", "tiles_pruned", "points_visited", "points_skipped",
         "points_updated", "tiles_resynced", "exchanges", "ticks_lookahead", "ticks_exchange",
-        "ticks_merge", "ticks_apply", "tick_hz", "ticks_wait", "reserved")]
+        "ticks_merge", "ticks_apply", "tick_hz", "ticks_wait", "reserved",
+        "ticks_merge_list", "ticks_merge_rank", "ticks_merge_walk", "ticks_merge_picks", "ticks_lookahead_copy",
+        "ticks_lookahead_steps", "ticks_exchange_poll", "ticks_exchange_keys", "merge_above", "merge_listed",
+        "merge_failures", "ticks_apply_loop", "ticks_lookahead_select", "reserved2_0", "reserved2_1",
+        "reserved2_2")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_ if not k.startswith("reserved")}
@@ -87,6 +92,8 @@ def lib() -> ctypes.CDLL:
         L.rfps_read_index_info.restype = ctypes.c_int
         L.rfps_read_telemetry.argtypes = [P(rfps_index), vp, P(rfps_telemetry)]
         L.rfps_read_telemetry.restype = ctypes.c_int
+        L.rfps_probe_exchange.argtypes = [P(rfps_index), i32, i32, i32, vp, P(ctypes.c_double)]
+        L.rfps_probe_exchange.restype = ctypes.c_int
         L.rfps_read_trace.argtypes = [P(rfps_index), vp, vp, i32, P(ctypes.c_double)]
         L.rfps_read_trace.restype = i32
         L.rfps_fps_plain_workspace_size.argtypes = [i32, i32]
@@ -253,6 +260,15 @@ def read_telemetry(index: Index) -> dict:
     _check(lib().rfps_read_telemetry(ctypes.byref(index.handle), _stream(index.device), ctypes.byref(t)),
            "rfps_read_telemetry")
     return t.as_dict()
+
+
+def probe_exchange(index: Index, words: int, rounds: int = 2000, groups: int = 0) -> float:
+    """rfps_probe_exchange: microseconds per bare exchange round of `words`
+    words per workgroup among `groups` workgroups (0 = one per compute unit)."""
+    us = ctypes.c_double(0.0)
+    _check(lib().rfps_probe_exchange(ctypes.byref(index.handle), int(groups), int(words), int(rounds),
+                                     _stream(index.device), ctypes.byref(us)), "rfps_probe_exchange")
+    return float(us.value)
 
 
 def read_trace(index: Index, cap: int = 1 << 17):

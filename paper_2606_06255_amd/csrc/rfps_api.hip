@@ -18,7 +18,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr uint32_t kKnownFlags =
-    RFPS_F_NO_PRUNE | RFPS_F_NO_POINT_SKIP | RFPS_F_TELEMETRY | RFPS_F_TRACE | RFPS_F_SINGLE_PICK | RFPS_F_SQRT | RFPS_F_UNFUSED;
+    RFPS_F_NO_PRUNE | RFPS_F_NO_POINT_SKIP | RFPS_F_TELEMETRY | RFPS_F_TRACE | RFPS_F_SINGLE_PICK | RFPS_F_SQRT | RFPS_F_UNFUSED |
+    RFPS_F_CLOCKS;
 constexpr int kDefaultLookahead = 2;
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -329,7 +330,8 @@ rfps_status rfps_sample(const rfps_index *index, int32_t m, int32_t start, const
         return st;
     if (m < 1 || m > index->n || start < 0 || start >= index->n || !out_idx || !params_valid(params))
         return RFPS_ERR_INVALID_ARG;
-    if (params && (params->flags & RFPS_F_UNFUSED) && (params->flags & (RFPS_F_TELEMETRY | RFPS_F_TRACE)))
+    if (params && (params->flags & RFPS_F_UNFUSED) &&
+        (params->flags & (RFPS_F_TELEMETRY | RFPS_F_TRACE | RFPS_F_CLOCKS)))
         return RFPS_ERR_UNSUPPORTED;
     const DeviceInfo *d = device_info();
     if (!d)
@@ -413,6 +415,39 @@ rfps_status rfps_read_telemetry(const rfps_index *index, void *stream, rfps_tele
     memcpy(out, h.tele, sizeof *out);
     const DeviceInfo *d = device_info();
     out->tick_hz = d ? (int64_t)d->wall_hz : 0;
+    return RFPS_OK;
+}
+
+rfps_status rfps_probe_exchange(const rfps_index *index, int32_t groups, int32_t words, int32_t rounds,
+                                void *stream, double *us_per_round)
+{
+    rfps_status st = check_index(index);
+    if (st != RFPS_OK)
+        return st;
+    if (!us_per_round || words < 1 || words > 16 || rounds < 1 || rounds > (1 << 20) || groups < 0)
+        return RFPS_ERR_INVALID_ARG;
+    const DeviceInfo *d = device_info();
+    if (!d)
+        return RFPS_ERR_DEVICE;
+    if (!d->ok)
+        return RFPS_ERR_UNSUPPORTED;
+    const int G = groups ? groups : std::min(d->cus, kMaxGroups);
+    if (G > d->cus || G > kMaxGroups)
+        return RFPS_ERR_INVALID_ARG;
+    const IndexView v = make_view(index->ws, index->n, index->n_vox, index->tile, index->shells);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    // the trace buffer's first two words take the ticks and the status
+    unsigned long long *out = v.trace;
+    unsigned long long host[2] = {0ull, 0ull};
+    const hipError_t e = launch_exchange_probe(v.board, G, words, rounds, out, reinterpret_cast<uint32_t *>(out + 1), s);
+    if (e == hipErrorCooperativeLaunchTooLarge)
+        return RFPS_ERR_UNSUPPORTED;
+    if (e != hipSuccess || hipStreamSynchronize(s) != hipSuccess ||
+        hipMemcpy(host, out, sizeof host, hipMemcpyDeviceToHost) != hipSuccess)
+        return RFPS_ERR_DEVICE;
+    if ((uint32_t)host[1] != 0)
+        return (rfps_status)(uint32_t)host[1];
+    *us_per_round = (double)host[0] / d->wall_hz * 1e6 / rounds;
     return RFPS_OK;
 }
 
@@ -527,7 +562,7 @@ rfps_status rfps_sample_batched(const float *xyz, int32_t n, const int32_t *offs
         batch > n || m_total < batch || m_total > n || !params_valid(params))
         return RFPS_ERR_INVALID_ARG;
     const uint32_t flags = params ? params->flags : 0u;
-    if (flags & (RFPS_F_NO_PRUNE | RFPS_F_SINGLE_PICK | RFPS_F_TRACE | RFPS_F_UNFUSED))
+    if (flags & (RFPS_F_NO_PRUNE | RFPS_F_SINGLE_PICK | RFPS_F_TRACE | RFPS_F_UNFUSED | RFPS_F_CLOCKS))
         return RFPS_ERR_UNSUPPORTED;
     const int fixed_n_vox = params ? params->n_vox : 0;
     const IndexLayout BL = layout_batch(n, batch, fixed_n_vox, use_shells(params));

@@ -33,7 +33,7 @@ constexpr int kRadixTile = kBlock * kRadixItems;
 constexpr int kScanItems = 16;       // elements per thread of the scan kernels
 constexpr int kScanChunk = kBlock * kScanItems;
 constexpr int kTraceCap = 1 << 17;   // iterations recorded by RFPS_F_TRACE
-constexpr int kTeleFields = 16;
+constexpr int kTeleFields = 32;
 // telemetry slots (rfps_telemetry field order)
 constexpr int kTeleExchanges = 8;
 constexpr int kTeleTicksLookahead = 9;
@@ -42,6 +42,8 @@ constexpr int kTeleTicksMerge = 11;
 constexpr int kTeleTicksApply = 12;
 constexpr int kTeleTickHz = 13;
 constexpr int kTeleTicksWait = 14;
+constexpr int kTeleSub = 16;        // eight finer clocks of the rounds (see rfps_telemetry)
+constexpr int kTeleMergeStats = 24; // listed-above, listed, failures summed over rounds
 
 // Status words live in the index header.  The build status is sticky for the
 // index; the sample status is cleared at the start of every sampling call.
@@ -432,6 +434,10 @@ hipError_t launch_rfps_unfused(const IndexView &v, int m, int start, uint32_t fl
 size_t rfps_rounds_static_lds(int R);
 hipError_t launch_rfps_rounds(const IndexView &v, int m, int start, const SampleLaunch &L, int32_t *out_idx,
                               float *out_d2, hipStream_t s);
+// Exchange floor probe (sample_rounds.hip): `rounds` bare exchanges of W
+// words among G workgroups; out[0] receives the ticks of workgroup 0.
+hipError_t launch_exchange_probe(unsigned long long *board, int G, int W, int rounds, unsigned long long *out,
+                                 uint32_t *status, hipStream_t s);
 // Writes -1 / NaN to all m outputs when the header records an error (sample_rfps.hip).
 hipError_t launch_sample_finalize(const IndexHeader *hdr, int m, int32_t *out_idx, float *out_d2, hipStream_t s);
 

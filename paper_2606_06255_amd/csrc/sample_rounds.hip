@@ -33,9 +33,10 @@
 //      other points of g are bounded by u_h (their local keys at step h
 //      assumed only l_1..l_{h-1}, which are picks); the later candidates of g
 //      are dropped, l_h is listed again with key t, and the merge goes on
-//      under the larger bound.  The merge sorts the candidates above the
-//      largest bound, certifies them in that order with all threads of the
-//      workgroup, and at a failure re-lists and resumes;
+//      under the larger bound.  The merge lists the candidates above the
+//      largest bound, finds with all threads of the workgroup their order and,
+//      for each, the listed candidates that would lower it, and then walks the
+//      order in one wavefront, re-listing at every failure;
 //   A  apply: all picks of the round update the true state (spherical test
 //      per tile and pick, point skip, strict update, tile-key resync).
 //
@@ -73,9 +74,24 @@ struct RoundArgs {
     const int32_t *order;        // [batch] clouds by decreasing cost
 };
 
-// Selections one round may settle (the merge stops there; a shorter round is
-// always valid).
-constexpr int kMaxRoundPicks = 512;
+// Candidates one merge lists, and so the selections one round may settle
+// (the merge stops there; a shorter round is always valid).
+constexpr int kList = 2 * kWave;
+constexpr int kMaxRoundPicks = kList;
+
+// Lane mask of the lanes where b holds.  (A ballot of a single comparison
+// uses the comparison's mask as it is; combining masks with & keeps it so.)
+__device__ __forceinline__ unsigned long long ballot64(bool b) { return __builtin_amdgcn_ballot_w64(b); }
+
+// Value of lane l of v (l uniform).
+__device__ __forceinline__ float lane_f32(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ uint32_t lane_u32(uint32_t v, int l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
 // Failed candidates a round re-lists before it ends (each failure lowers a
 // listed key, so the loop ends anyway; this caps the work of one round).
 constexpr uint32_t kMaxFailures = 64;
@@ -179,7 +195,11 @@ struct RoundShared {
     uint32_t scan[kWavesPerBlock];
     unsigned long long red2[kWavesPerBlock];
     uint32_t abort, list_n, npick, mcount, pfront, pback, mtotal, msel;
-    float cminw[2][kWavesPerBlock][kWave];  // merge: partial true distances of one chunk of 64 positions
+    float4 lq[kList];                   // merge: listed candidates' coordinates and listed distance
+    uint32_t lkl[kList];                // merge: low halves of their keys (~ original index)
+    unsigned long long lset[kList][2];  // merge: listed candidates with larger keys that would lower each one
+    uint32_t lrank[kList];              // merge: rank of each listed candidate in key order
+    uint32_t rep;                       // merge: some listed keys are equal (repeats of one point)
     uint32_t hist[256];    // merge: candidates per key bucket
     uint32_t my[6 * 8 + 2];  // this workgroup's slot payload (R <= 8)
 };
@@ -188,6 +208,10 @@ struct RoundShared {
 struct RoundTele {
     unsigned long long tests = 0, pruned = 0, visited = 0, skipped = 0, updated = 0, resync = 0;
     unsigned long long ph[5] = {0, 0, 0, 0, 0};  // lookahead, exchange, merge, apply, exchange wait
+    // finer clocks: merge list / rank / walk / picks, lookahead copy / steps,
+    // exchange poll / keys; and the merge's list lengths and failures
+    unsigned long long sub[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // + apply tile loop, lookahead selects
+    unsigned long long above = 0, listed = 0, fails = 0;
     unsigned long long rounds = 0;
 };
 
@@ -367,8 +391,15 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 tbestl[lt] = tbest[lt];
                 tflag[lt] = 0;
             }
+            if (clocks) {
+                const unsigned long long t = wall_clock64();
+                tl.sub[4] += t - t_mark;
+                tl.sub[5] -= t;  // the steps end at the phase mark below
+            }
             for (int s = 0; s <= R; ++s) {
                 // arg max over the local tile keys (key and tile travel together)
+                if (clocks)
+                    tl.sub[9] -= wall_clock64();
                 unsigned long long lk = 0, lk2 = 0;  // the lane's two largest tile keys
                 uint32_t lt_best = 0;
                 for (int lt = lane; lt < ntl; lt += kWave) {
@@ -392,6 +423,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                             for (int w = 0; w < 6; ++w)
                                 sh.my[6 * q + w] = 0;
                     }
+                    if (clocks)
+                        tl.sub[9] += wall_clock64();
                     break;
                 }
                 const uint32_t bt = (uint32_t)__builtin_amdgcn_readlane((int)lt_best, __ffsll((long long)hit) - 1);
@@ -418,6 +451,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     sh.my[6 * s + 4] = po[p];
                     sh.my[6 * s + 5] = (uint32_t)(ru >> 32);  // runner-up d2
                 }
+                if (clocks)
+                    tl.sub[9] += wall_clock64();
                 // local update with l_s (pruned against the local thresholds)
                 for (int lt0 = 0; lt0 < ntl; lt0 += kWave) {
                     const int lt = lt0 + lane;
@@ -463,6 +498,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         if (clocks) {
             const unsigned long long t = wall_clock64();
             tl.ph[0] += t - t_mark;
+            tl.sub[5] += t;
             t_mark = t;
         }
 
@@ -538,6 +574,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 sh.abort = 1;
             if (clocks && t_first)
                 tl.ph[4] += wall_clock64() - t_first;
+            if (clocks)
+                tl.sub[6] += wall_clock64() - t_mark;
         }
         __syncthreads();
         if (!sh.abort) {
@@ -569,6 +607,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 sh.mcount = 0;
                 sh.pfront = 0;
                 sh.pback = 0;
+                sh.rep = 0;
             }
             sh.hist[tid] = 0;
         }
@@ -586,6 +625,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         if (clocks) {
             const unsigned long long t = wall_clock64();
             tl.ph[1] += t - t_mark;
+            tl.sub[7] += t - t_mark;  // the poll's share is taken off below
             t_mark = t;
         }
 
@@ -595,10 +635,17 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         // every earlier pick of the round) still equals its local distance.
         // Taking the group with the largest bound B_g at every step visits
         // exactly this order until the largest published bound S* = max_g
-        // k_{R+1} is reached, where it stops; so the candidates above S* are
-        // compacted, put in order by counting and certified 64 positions at a
-        // time, and a failed candidate is re-listed (below) instead of ending
-        // the round.
+        // k_{R+1} is reached, where it stops.  So the candidates above S* are
+        // listed (at most kList: a longer list is cut at a key boundary, and
+        // the bound rises to the largest key left out), and for every listed
+        // candidate its rank in key order and the set of listed candidates
+        // that would lower it (state value of their distance below its listed
+        // distance) are computed once, by all wavefronts.  Certification is
+        // then a walk over the order in one wavefront: the first candidate
+        // with a member of its set at an earlier position fails.  A failed
+        // candidate is re-listed (below) and the walk resumes; distances
+        // between candidates do not change, so only the re-listed candidate's
+        // own set is computed again, against its new key.
         {
             unsigned long long smax = 0, hmax = 0;
 #pragma unroll
@@ -617,14 +664,9 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 k = c < G * R ? bkey[g * (R + 1) + c % R] : 0ull;
                 return c < G * R && (k > smax || (k == smax && bkey[g * (R + 1) + R] == smax));
             };
-            // Only the first positions of the order are usually needed.  The
-            // candidates above S* are compacted (in any order) while a
+            // The candidates above S* are compacted (in any order) while a
             // histogram of their keys' high halves (distance bits, between S*
-            // and the largest key) is counted; with more than kSelect of them,
-            // the bucket above which at least kSelect lie splits the list into
-            // a front (keys >= kthr) that is put in order and certified first,
-            // and the rest, ordered only if the round gets that far.
-            constexpr uint32_t kSelect = 128;
+            // and the largest key) is counted.
             const uint32_t hlo = (uint32_t)(smax >> 32);
             const uint32_t span = (uint32_t)(hmax >> 32) - hlo;
             const int bits = span ? 32 - __clz((int)span) : 0;
@@ -644,12 +686,19 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     skey[pos] = k;
                     sidx[pos] = (uint32_t)c;
                     atomicAdd(&sh.hist[((uint32_t)(k >> 32) - hlo) >> bshift], 1u);
+                    if (c % R != 0 && k == bkey[(c / R) * (R + 1) + c % R - 1])
+                        sh.rep = 1;  // a repeat of the group's previous candidate
                 }
             }
             __syncthreads();
             const uint32_t L = sh.mcount;
-            uint32_t Lf = L;
-            if (L > kSelect) {
+            uint32_t *ord = reinterpret_cast<uint32_t *>(bkey);  // bkey is not read again this round
+            // scur: every listed key is above it (or equals S*, see taken) and
+            // every point left out of the list has its true key at most it
+            unsigned long long scur = smax;
+            uint32_t W = L;  // the list: skey / sidx [0, W)
+            if (L > (uint32_t)kList) {
+                // msel: the highest bucket whose suffix holds kList candidates
                 if (wave == 0) {
                     uint32_t c4 = 0;
 #pragma unroll
@@ -661,14 +710,13 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                         const uint32_t o = (uint32_t)__shfl_down((int)suf, off, kWave);
                         suf += lane + off < kWave ? o : 0u;
                     }
-                    // the last lane whose suffix holds kSelect (lane 0's holds L)
-                    const unsigned long long enough = __ballot(suf >= kSelect);
+                    const unsigned long long enough = __ballot(suf >= (uint32_t)kList);
                     const int lt = 63 - __clzll((long long)enough);
                     if (lane == lt) {
                         uint32_t acc = suf - c4;
                         for (int b = 3; b >= 0; --b) {
                             acc += sh.hist[4 * lane + b];
-                            if (acc >= kSelect) {
+                            if (acc >= (uint32_t)kList) {
                                 sh.msel = (uint32_t)(4 * lane + b);
                                 sh.mtotal = acc;
                                 break;
@@ -677,11 +725,13 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     }
                 }
                 __syncthreads();
-                Lf = sh.mtotal;
-                // partition: the front to [0, Lf), the rest behind it (the
-                // order inside either part is irrelevant: only repeats of one
-                // point have equal keys)
                 const uint32_t bsel = sh.msel;
+                const uint32_t above = sh.mtotal - sh.hist[bsel];  // fewer than kList
+                // the buckets above msel are listed when they hold anything;
+                // else msel alone holds kList or more (keys that agree in their
+                // high bits), and its candidates are put in order below
+                const uint32_t bfront = above ? bsel + 1 : bsel;
+                const uint32_t nfront = above ? above : sh.mtotal;
                 constexpr int kParts = (kMaxGroups * R + kBlock - 1) / kBlock;  // L <= G * R
                 unsigned long long pk_[kParts];
                 uint32_t pc_[kParts], pp_[kParts];
@@ -691,20 +741,13 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     const bool in = i < L;
                     pk_[u] = in ? skey[i] : 0ull;
                     pc_[u] = in ? sidx[i] : 0u;
-                    const bool front = in && (((uint32_t)(pk_[u] >> 32) - hlo) >> bshift) >= bsel;
-                    const unsigned long long fm = __ballot(front), bm = __ballot(in && !front);
-                    uint32_t fb = 0, bb = 0;
-                    if (lane == 0) {
-                        if (fm)
-                            fb = atomicAdd(&sh.pfront, (uint32_t)__popcll(fm));
-                        if (bm)
-                            bb = atomicAdd(&sh.pback, (uint32_t)__popcll(bm));
-                    }
+                    const bool front = in && (((uint32_t)(pk_[u] >> 32) - hlo) >> bshift) >= bfront;
+                    const unsigned long long fm = __ballot(front);
+                    uint32_t fb = 0;
+                    if (lane == 0 && fm)
+                        fb = atomicAdd(&sh.pfront, (uint32_t)__popcll(fm));
                     fb = (uint32_t)__shfl((int)fb, 0, kWave);
-                    bb = (uint32_t)__shfl((int)bb, 0, kWave);
-                    pp_[u] = !in ? 0xffffffffu
-                                 : (front ? fb + (uint32_t)__popcll(fm & below)
-                                          : Lf + bb + (uint32_t)__popcll(bm & below));
+                    pp_[u] = front ? fb + (uint32_t)__popcll(fm & below) : 0xffffffffu;
                 }
                 __syncthreads();
 #pragma unroll
@@ -715,279 +758,338 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     }
                 }
                 __syncthreads();
+                // every candidate left out lies in a bucket below bfront
+                const unsigned long long edge = (unsigned long long)(hlo + (bfront << bshift)) << 32;
+                if (edge)
+                    scur = umax64(scur, edge - 1ull);
+                W = nfront;
+                if (!above && nfront > (uint32_t)kList) {
+                    // order the bucket by whole keys (equal keys: list order)
+                    // and keep its first kList, cut between different keys
+                    for (uint32_t i = tid; i < nfront; i += kBlock) {
+                        const unsigned long long ki = skey[i];
+                        uint32_t r = 0;
+                        for (uint32_t q = 0; q < nfront; ++q) {
+                            const unsigned long long kq = skey[q];
+                            r += (kq > ki || (kq == ki && q < i)) ? 1u : 0u;
+                        }
+                        if (r <= (uint32_t)kList)
+                            ord[r] = i;
+                    }
+                    __syncthreads();
+                    W = kList;
+                    while (W > 1 && skey[ord[W - 1]] == skey[ord[W]])
+                        --W;  // equal keys are repeats of one point (at most R)
+                    scur = umax64(scur, skey[ord[W]]);
+                    unsigned long long kk = 0;
+                    uint32_t cc = 0;
+                    if ((uint32_t)tid < W) {
+                        kk = skey[ord[tid]];
+                        cc = sidx[ord[tid]];
+                    }
+                    __syncthreads();
+                    if ((uint32_t)tid < W) {
+                        skey[tid] = kk;
+                        sidx[tid] = cc;
+                    }
+                    __syncthreads();
+                }
             }
-            // Order by counting: the rank of a candidate within a part of the
-            // list is the number of larger keys plus the number of equal keys
-            // (repeats of one point) earlier in the part.  Every thread keeps
-            // its candidates' distances in registers and reads the part once,
-            // counting larger and equal distances (the high halves of the
-            // keys); a candidate whose distance occurs more than once in the
-            // part is then ranked again on whole keys.
-            uint32_t *ord = reinterpret_cast<uint32_t *>(bkey);  // bkey is not read again this round
-            auto rank_part = [&](auto per_thread, uint32_t lo, uint32_t hi, auto key_at, auto dist_at) {
-                constexpr int U = decltype(per_thread)::value;
-                uint32_t mh[U], gt[U], eq[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const uint32_t i = lo + tid + kBlock * u;
-                    mh[u] = i < hi ? dist_at(i) : 0u;
-                    gt[u] = 0;
-                    eq[u] = 0;
-                }
-                auto count = [&](uint32_t kh) {
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        gt[u] += kh > mh[u] ? 1u : 0u;
-                        eq[u] += kh == mh[u] ? 1u : 0u;
+            const uint32_t pmax = min(W, (uint32_t)(job.m - j));
+            unsigned long long t_sub = 0;
+            if (clocks) {
+                t_sub = wall_clock64();
+                tl.sub[0] += t_sub - t_mark;
+                tl.above += L;
+                tl.listed += W;
+            }
+
+            // Ranks and lowering sets.  Lanes take listed candidates q (two
+            // chunks of 64), wavefronts take candidates i (two at a time).
+            // For each i, ballots give the set of q with a larger key that
+            // would lower i (state value of their distance below i's listed
+            // distance) and i's rank in key order (larger keys, then equal
+            // keys listed before it: only repeats of one point are equal).
+            // Every ballot is of a single comparison, so its lane mask is
+            // used as it is.
+            if ((uint32_t)tid < W) {
+                const uint32_t c = sidx[tid];
+                const unsigned long long k = skey[tid];
+                sh.lq[tid] = make_float4(cx[c], cy[c], cz[c], __uint_as_float((uint32_t)(k >> 32)));
+                sh.lkl[tid] = (uint32_t)k;
+            }
+            __syncthreads();
+            const bool two = W > (uint32_t)kWave;  // a second chunk of candidates
+            const unsigned long long v0 = ballot64((uint32_t)lane < W);
+            const unsigned long long v1 = ballot64((uint32_t)lane + kWave < W);
+            const float4 q0 = sh.lq[lane];
+            const float4 q1 = sh.lq[two ? lane + kWave : lane];
+            const unsigned long long k0 = ((unsigned long long)__float_as_uint(q0.w) << 32) | sh.lkl[lane];
+            const unsigned long long k1 =
+                ((unsigned long long)__float_as_uint(q1.w) << 32) | sh.lkl[two ? lane + kWave : lane];
+            {
+                const bool rep = sh.rep != 0;
+                auto one = [&](uint32_t i, uint32_t &s0l, uint32_t &s0h, uint32_t &s1l, uint32_t &s1h, uint32_t &rk) {
+                    const float4 qi = sh.lq[i];
+                    const unsigned long long ki = ((unsigned long long)__float_as_uint(qi.w) << 32) | sh.lkl[i];
+                    const float d0 = sqdist(qi.x, qi.y, qi.z, q0.x, q0.y, q0.z);
+                    bool b0 = d0 < qi.w;
+                    if (euclid && b0)
+                        b0 = sqrt_class_top(d0) < qi.w;
+                    const unsigned long long g0 = ballot64(k0 > ki) & v0;
+                    const unsigned long long m0 = ballot64(b0) & g0;
+                    rk = (uint32_t)__popcll(g0);
+                    unsigned long long m1 = 0;
+                    if (two) {
+                        const float d1 = sqdist(qi.x, qi.y, qi.z, q1.x, q1.y, q1.z);
+                        bool b1 = d1 < qi.w;
+                        if (euclid && b1)
+                            b1 = sqrt_class_top(d1) < qi.w;
+                        const unsigned long long g1 = ballot64(k1 > ki) & v1;
+                        m1 = ballot64(b1) & g1;
+                        rk += (uint32_t)__popcll(g1);
                     }
+                    if (rep) {
+                        // equal keys listed before i
+                        const unsigned long long below_i =
+                            (i & (kWave - 1)) ? ~0ull >> (kWave - (i & (kWave - 1))) : 0ull;
+                        const unsigned long long e0 = ballot64(k0 == ki) & v0 & (i >= (uint32_t)kWave ? ~0ull : below_i);
+                        rk += (uint32_t)__popcll(e0);
+                        if (two) {
+                            const unsigned long long e1 =
+                                ballot64(k1 == ki) & v1 & (i >= (uint32_t)kWave ? below_i : 0ull);
+                            rk += (uint32_t)__popcll(e1);
+                        }
+                    }
+                    s0l = (uint32_t)m0;
+                    s0h = (uint32_t)(m0 >> 32);
+                    s1l = (uint32_t)m1;
+                    s1h = (uint32_t)(m1 >> 32);
                 };
-                uint32_t q0 = lo;
-                for (; q0 + 8 <= hi; q0 += 8) {
-                    uint32_t kh[8];
-#pragma unroll
-                    for (int v = 0; v < 8; ++v)
-                        kh[v] = dist_at(q0 + v);
-#pragma unroll
-                    for (int v = 0; v < 8; ++v)
-                        count(kh[v]);
+                uint32_t r0l = 0, r0h = 0, r1l = 0, r1h = 0, rrk = 0;
+                int t = 0;
+                for (uint32_t i = (uint32_t)wave; i < W; i += 2 * kWavesPerBlock, t += 2) {
+                    // two independent candidates per pass (the second may lie
+                    // past the list: its results are not kept)
+                    const uint32_t i2 = i + kWavesPerBlock < W ? i + kWavesPerBlock : i;
+                    uint32_t a0l, a0h, a1l, a1h, ark, b0l, b0h, b1l, b1h, brk;
+                    one(i, a0l, a0h, a1l, a1h, ark);
+                    one(i2, b0l, b0h, b1l, b1h, brk);
+                    const bool ma = lane == t, mb = lane == t + 1;
+                    r0l = ma ? a0l : mb ? b0l : r0l;
+                    r0h = ma ? a0h : mb ? b0h : r0h;
+                    r1l = ma ? a1l : mb ? b1l : r1l;
+                    r1h = ma ? a1h : mb ? b1h : r1h;
+                    rrk = ma ? ark : mb ? brk : rrk;
                 }
-                for (; q0 < hi; ++q0)
-                    count(dist_at(q0));
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const uint32_t i = lo + tid + kBlock * u;
-                    if (i < hi) {
-                        uint32_t r = gt[u];
-                        if (eq[u] > 1) {
-                            // equal distances: whole keys decide, list position
-                            // among repeats of one point
-                            const unsigned long long mk = key_at(i);
-                            r = 0;
-                            for (uint32_t q = lo; q < hi; ++q) {
-                                const unsigned long long kq = key_at(q);
-                                r += (kq > mk || (kq == mk && q < i)) ? 1u : 0u;
-                            }
-                        }
-                        ord[lo + r] = sidx[i];
-                    }
+                // lane t holds the results of this wavefront's t-th candidate
+                const uint32_t i = (uint32_t)wave + (uint32_t)kWavesPerBlock * (uint32_t)lane;
+                if (i < W) {
+                    sh.lset[i][0] = ((unsigned long long)r0h << 32) | r0l;
+                    sh.lset[i][1] = ((unsigned long long)r1h << 32) | r1l;
+                    sh.lrank[i] = rrk;
                 }
-            };
-            auto rank_range = [&](uint32_t lo, uint32_t hi, auto key_at, auto dist_at) {
-                const uint32_t n = hi - lo;
-                if (n <= kBlock)
-                    rank_part(std::integral_constant<int, 1>(), lo, hi, key_at, dist_at);
-                else if (n <= 2 * kBlock)
-                    rank_part(std::integral_constant<int, 2>(), lo, hi, key_at, dist_at);
-                else if (n <= 4 * kBlock)
-                    rank_part(std::integral_constant<int, 4>(), lo, hi, key_at, dist_at);
-                else
-                    rank_part(std::integral_constant<int, 8>(), lo, hi, key_at, dist_at);
-                __syncthreads();
-            };
-            rank_range(
-                0, Lf, [&](uint32_t i) { return skey[i]; },
-                [&](uint32_t i) { return reinterpret_cast<const uint32_t *>(skey)[2 * i + 1]; });
-            const uint32_t pmax = min(min(L, (uint32_t)kMaxRoundPicks), (uint32_t)(job.m - j));
-            // certifies positions [from, lim) of the order; returns the end of
-            // the certified prefix
-            // certifies positions [from, lim) of the order (their coordinates
-            // staged unless `staged`); returns the end of the certified prefix,
-            // and at a failure its candidate and true distance (cfail, tfail).
-            // Every wave takes the earlier positions q = w mod 4 and writes its
-            // partial minima; after one barrier every wave combines them and
-            // finds the first failure itself.  The partial minima alternate
-            // between two buffers, so a wave that runs ahead into the next chunk
-            // cannot overwrite those still being read.
-            uint32_t cpar = 0, cfail = 0;
-            float tfail = 0.0f;
-            auto certify = [&](uint32_t from, uint32_t lim, bool staged) -> uint32_t {
-                if (!staged) {
-                    // coordinates in merge order (those of the certified prefix are the picks)
-                    for (uint32_t e = from + tid; e < lim; e += kBlock) {
-                        const uint32_t c = ord[e];
-                        pkx[e] = cx[c];
-                        pky[e] = cy[c];
-                        pkz[e] = cz[c];
-                    }
-                    __syncthreads();
-                }
-                uint32_t P = from;
-                for (uint32_t base = from; base < lim; base += kWave) {
-                    const uint32_t n = min((uint32_t)kWave, lim - base);
-                    // true distance of every position of the chunk: its local
-                    // value, lowered by every earlier position (the earlier ones
-                    // are all picks if this one is reached; the group's own ones
-                    // change nothing)
-                    const uint32_t e = base + lane;
-                    const bool in = (uint32_t)lane < n;
-                    const uint32_t ce = in ? ord[e] : 0u;
-                    const float le = in ? cld[ce] : INFINITY;
-                    {
-                        const float x = pkx[in ? e : base], y = pky[in ? e : base], z = pkz[in ? e : base];
-                        float t = le;
-                        const uint32_t qend = base + n - 1;  // no position reaches past it
-                        uint32_t q = wave;
-                        for (; q + 3 * kWavesPerBlock < qend; q += 4 * kWavesPerBlock) {
-                            float sx[4], sy[4], sz[4];
-#pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                sx[v] = pkx[q + v * kWavesPerBlock];
-                                sy[v] = pky[q + v * kWavesPerBlock];
-                                sz[v] = pkz[q + v * kWavesPerBlock];
-                            }
-#pragma unroll
-                            for (int v = 0; v < 4; ++v)
-                                if (q + v * kWavesPerBlock < e)
-                                    t = min_dist(t, sqdist(x, y, z, sx[v], sy[v], sz[v]), euclid);
-                        }
-                        for (; q < qend; q += kWavesPerBlock)
-                            if (q < e)
-                                t = min_dist(t, sqdist(x, y, z, pkx[q], pky[q], pkz[q]), euclid);
-                        sh.cminw[cpar][wave][lane] = t;
-                    }
-                    __syncthreads();
-                    float tt = sh.cminw[cpar][0][lane];
-#pragma unroll
-                    for (int w = 1; w < kWavesPerBlock; ++w)
-                        tt = fminf(tt, sh.cminw[cpar][w][lane]);
-                    cpar ^= 1u;
-                    const unsigned long long fm = __ballot(in && tt != le);
-                    if (fm) {
-                        const int first = __ffsll((long long)fm) - 1;
-                        cfail = (uint32_t)__builtin_amdgcn_readlane((int)ce, first);
-                        tfail = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tt), first));
-                        P = base + (uint32_t)first;
+            }
+            __syncthreads();
+            if (clocks) {
+                const unsigned long long t = wall_clock64();
+                tl.sub[1] += t - t_sub;
+                t_sub = t;
+            }
+
+            // Certification walk (wavefront 0), in registers: lane l holds
+            // listed candidates l and l + 64 (key, set, rank, coordinates).
+            // The list stays in key order, so "earlier" means "larger key":
+            // a live candidate fails when a live member of its set exists
+            // (every live candidate with a larger key is a pick if the walk
+            // reaches it), the first failure is the failing candidate with
+            // the largest key, and the picks before it are the live
+            // candidates with larger keys, which stay live from then on.
+            if (wave == 0) {
+                unsigned long long s00 = sh.lset[lane][0], s01 = sh.lset[lane][1];
+                unsigned long long s10 = two ? sh.lset[lane + kWave][0] : 0ull;
+                unsigned long long s11 = two ? sh.lset[lane + kWave][1] : 0ull;
+                const uint32_t rk0 = sh.lrank[lane], rk1 = two ? sh.lrank[lane + kWave] : 0u;
+                const uint32_t cc0 = sidx[lane], cc1 = two ? sidx[lane + kWave] : 0u;
+                unsigned long long kc0 = k0, kc1 = k1;      // current listed keys
+                unsigned long long L0 = v0, L1 = v1;        // live (listed) candidates
+                unsigned long long X0 = 0, X1 = 0;          // re-listed or dropped as a group's later candidate
+                unsigned long long R0 = 0, R1 = 0;          // re-listed
+                uint32_t nfail = 0, P;
+                for (;;) {
+                    const unsigned long long F0 = ballot64(((s00 & L0) | (s01 & L1)) != 0ull) & L0;
+                    const unsigned long long F1 = ballot64(((s10 & L0) | (s11 & L1)) != 0ull) & L1;
+                    if (!(F0 | F1)) {
+                        P = min((uint32_t)(__popcll(L0) + __popcll(L1)), pmax);
                         break;
                     }
-                    P = base + n;
-                }
-                return P;
-            };
-            // Certify in order.  When the candidate at position P fails, its
-            // true distance t (exact for the picks so far) is known, and its
-            // group's other points are bounded by that candidate's runner-up:
-            // the bound S rises to it, the group's later candidates (whose
-            // local keys assumed this one picked) and every key <= S leave the
-            // list, the failed candidate goes back in with key t if t > S, and
-            // certification resumes at P.  Every listed key bounds its
-            // candidate's true key and S bounds every unlisted point, so the
-            // first listed candidate is the next selection whenever its true
-            // key equals its listed key.  The part behind the front is
-            // ordered when certification reaches it or a failure leaves part
-            // of it above S.
-            const unsigned long long kfront = L > Lf ? (unsigned long long)(hlo + (sh.msel << bshift)) << 32 : 0ull;
-            unsigned long long scur = smax;
-            uint32_t P = 0, lim_ord = Lf, nfail = 0;
-            bool back_alive = Lf < L, staged = false;
-            uint32_t *tmp = ord + L;  // rebuild buffer (the key region holds 2 * G * (R + 1) words)
-            // ranks the part behind the front into ord[Lf, L) (all its keys are
-            // smaller).  The staged pick coordinates share their words with the
-            // stored keys, so these keys are formed again from the candidates'
-            // distances and indices.
-            auto rank_back = [&]() {
-                rank_range(
-                    Lf, L,
-                    [&](uint32_t i) {
-                        const uint32_t c = sidx[i];
-                        return ((unsigned long long)__float_as_uint(cld[c]) << 32) | (~corig[c]);
-                    },
-                    [&](uint32_t i) { return __float_as_uint(cld[sidx[i]]); });
-            };
-            for (;;) {
-                const uint32_t lim = min(lim_ord, pmax);
-                P = certify(P, lim, staged);
-                staged = false;
-                if (P == lim) {
-                    if (P == lim_ord && back_alive && P < pmax) {
-                        // the whole front holds: order the part behind it and
-                        // go on
-                        rank_back();
-                        lim_ord = L;
-                        staged = false;
-                        back_alive = false;
-                        continue;
+                    // the failing candidate with the largest key
+                    const unsigned long long bit = 1ull << lane;
+                    const unsigned long long kf = wave_max_u64(umax64((F0 & bit) ? kc0 : 0ull, (F1 & bit) ? kc1 : 0ull));
+                    const unsigned long long h0 = ballot64(kc0 > kf) & L0, h1 = ballot64(kc1 > kf) & L1;
+                    P = (uint32_t)(__popcll(h0) + __popcll(h1));
+                    if (P >= pmax) {
+                        P = pmax;
+                        break;
                     }
-                    break;
-                }
-                const uint32_t cf = cfail;
-                const float tf = tfail;
-                const unsigned long long kt = ((unsigned long long)__float_as_uint(tf) << 32) | (~corig[cf]);
-                scur = umax64(scur, ((unsigned long long)crun[cf] << 32) | 0xffffffffull);
-                if (++nfail > kMaxFailures)
-                    break;
-                if (back_alive && scur < kfront) {
-                    // part of the rest can still be taken: order it behind the
-                    // front first (the front is still as ranked)
-                    rank_back();
-                    lim_ord = L;
-                }
-                back_alive = false;
-                if (wave == 0) {
-                    // stable compaction of ord(P, lim_ord) into tmp with cf inserted
+                    if (++nfail > kMaxFailures)
+                        break;
+                    const unsigned long long e0 = ballot64(kc0 == kf) & F0;
+                    const uint32_t fi = e0 ? (uint32_t)(__ffsll((long long)e0) - 1)
+                                           : (uint32_t)kWave + (uint32_t)(__ffsll((long long)(ballot64(kc1 == kf) & F1)) - 1);
+                    const bool fh = fi >= (uint32_t)kWave;
+                    const int fl = (int)(fi & (kWave - 1));
+                    const float xf = lane_f32(fh ? q1.x : q0.x, fl), yf = lane_f32(fh ? q1.y : q0.y, fl),
+                                zf = lane_f32(fh ? q1.z : q0.z, fl);
+                    const unsigned long long sfl = fh ? s10 : s00, sfh = fh ? s11 : s01;
+                    const unsigned long long sf0 = ((unsigned long long)lane_u32((uint32_t)(sfl >> 32), fl) << 32) |
+                                                   lane_u32((uint32_t)sfl, fl);
+                    const unsigned long long sf1 = ((unsigned long long)lane_u32((uint32_t)(sfh >> 32), fl) << 32) |
+                                                   lane_u32((uint32_t)sfh, fl);
+                    const uint32_t cf = lane_u32(fh ? cc1 : cc0, fl);
+                    // its true distance: the listed distance lowered by the
+                    // live members of its set (all of them picks)
+                    const float d0 = sqdist(xf, yf, zf, q0.x, q0.y, q0.z), d1 = sqdist(xf, yf, zf, q1.x, q1.y, q1.z);
+                    float tv = INFINITY;
+                    if ((sf0 & L0) & bit)
+                        tv = min_dist(tv, d0, euclid);
+                    if ((sf1 & L1) & bit)
+                        tv = min_dist(tv, d1, euclid);
+                    const float tf = fminf(wave_min_dist(tv), __uint_as_float((uint32_t)(kf >> 32)));
+                    const unsigned long long kt = ((unsigned long long)__float_as_uint(tf) << 32) | (uint32_t)kf;
+                    scur = umax64(scur, ((unsigned long long)crun[cf] << 32) | 0xffffffffull);
                     const uint32_t gf = cf / R, hf = cf % R;
+                    // the group's later candidates (their local keys assumed
+                    // this one picked) and every key <= the bound leave; the
+                    // picks so far (h0, h1: the live keys above it) stay
+                    const unsigned long long g0 = ballot64(cc0 / R == gf) & ballot64(cc0 % R > hf) & L0 & ~h0;
+                    const unsigned long long g1 = ballot64(cc1 / R == gf) & ballot64(cc1 % R > hf) & L1 & ~h1;
+                    X0 |= g0;
+                    X1 |= g1;
+                    L0 &= ~((g0 | ballot64(kc0 <= scur)) & ~h0);
+                    L1 &= ~((g1 | ballot64(kc1 <= scur)) & ~h1);
+                    // the failed candidate goes back in with key kt if that is
+                    // above the bound; its set is taken again against tf
                     const bool put = kt > scur;
-                    bool placed = !put;
-                    uint32_t nk = 0, posc = 0;
-                    const unsigned long long below = lane ? (~0ull >> (kWave - lane)) : 0ull;
-                    for (uint32_t q0 = P + 1; q0 < lim_ord; q0 += kWave) {
-                        const uint32_t q = q0 + lane;
-                        const bool in = q < lim_ord;
-                        const uint32_t cq = in ? ord[q] : 0u;
-                        const unsigned long long kq =
-                            in ? ((unsigned long long)__float_as_uint(cld[cq]) << 32) | (~corig[cq]) : 0ull;
-                        const bool keep = in && kq > scur && !(cq / R == gf && cq % R > hf);
-                        const unsigned long long m = __ballot(keep);
-                        uint32_t shift = placed ? 1u : 0u;
-                        if (!placed) {
-                            const unsigned long long lm = __ballot(keep && kq < kt);
-                            if (lm) {
-                                const int first = __ffsll((long long)lm) - 1;
-                                posc = nk + (uint32_t)__popcll(m & (first ? (~0ull >> (kWave - first)) : 0ull));
-                                placed = true;
-                                shift = lane >= first ? 1u : 0u;
-                            }
+                    if (fh) {
+                        const unsigned long long fb = 1ull << fl;
+                        L1 = put ? (L1 | fb) : (L1 & ~fb);
+                        X1 |= fb;
+                        R1 |= fb;
+                        if (lane == fl)
+                            kc1 = kt;
+                    } else {
+                        const unsigned long long fb = 1ull << fl;
+                        L0 = put ? (L0 | fb) : (L0 & ~fb);
+                        X0 |= fb;
+                        R0 |= fb;
+                        if (lane == fl)
+                            kc0 = kt;
+                    }
+                    bool b0 = d0 < tf, b1 = d1 < tf;
+                    if (euclid) {
+                        b0 = b0 && sqrt_class_top(d0) < tf;
+                        b1 = b1 && sqrt_class_top(d1) < tf;
+                    }
+                    const unsigned long long n0 = ballot64(b0) & ballot64(kc0 > kt) & v0;
+                    const unsigned long long n1 = ballot64(b1) & ballot64(kc1 > kt) & v1;
+                    // candidates now above it no longer have it earlier
+                    const unsigned long long above = fh ? ~(1ull << fl) : ~0ull, abovel = fh ? ~0ull : ~(1ull << fl);
+                    if (kc0 > kt) {
+                        s00 &= abovel;
+                        s01 &= above;
+                    }
+                    if (kc1 > kt) {
+                        s10 &= abovel;
+                        s11 &= above;
+                    }
+                    if (lane == fl) {
+                        if (fh) {
+                            s10 = n0;
+                            s11 = n1;
+                        } else {
+                            s00 = n0;
+                            s01 = n1;
                         }
-                        if (keep)
-                            tmp[nk + (uint32_t)__popcll(m & below) + (put ? shift : 0u)] = cq;
-                        nk += (uint32_t)__popcll(m);
                     }
-                    if (put && !placed)
-                        posc = nk;  // below every kept key
-                    if (put && lane == 0)
-                        tmp[posc] = cf;
-                    if (lane == 0) {
-                        sh.mtotal = P + nk + (put ? 1u : 0u);
-                        cld[cf] = tf;  // its listed key from now on
+                    if (lane == 0)
+                        cld[cf] = tf;  // its listed (and, once certified, output) distance
+                }
+                // Order of the live candidates by current key.  A candidate
+                // whose key never changed has its list rank less the
+                // re-listed or group-dropped candidates ranked above it
+                // (every other candidate that left the list lies below all
+                // live ones), plus the re-listed live candidates above it; a
+                // re-listed one counts the live keys above its own.
+                uint32_t lr0 = rk0, lr1 = rk1;
+                unsigned long long xs0 = X0, xs1 = X1;
+                while (xs0 | xs1) {
+                    const bool qh = xs0 == 0ull;
+                    const int ql = __ffsll((long long)(qh ? xs1 : xs0)) - 1;
+                    if (qh)
+                        xs1 &= xs1 - 1;
+                    else
+                        xs0 &= xs0 - 1;
+                    const uint32_t rq = lane_u32(qh ? rk1 : rk0, ql);
+                    const unsigned long long kv = qh ? kc1 : kc0;
+                    const unsigned long long kq =
+                        ((unsigned long long)lane_u32((uint32_t)(kv >> 32), ql) << 32) | lane_u32((uint32_t)kv, ql);
+                    const bool rel_live = ((qh ? R1 & L1 : R0 & L0) >> ql) & 1ull;
+                    lr0 = lr0 - (rq < rk0 ? 1u : 0u) + ((rel_live && kq > kc0) ? 1u : 0u);
+                    lr1 = lr1 - (rq < rk1 ? 1u : 0u) + ((rel_live && kq > kc1) ? 1u : 0u);
+                }
+                // a re-listed live candidate: the live keys above its own
+                unsigned long long rs0 = R0 & L0, rs1 = R1 & L1;
+                while (rs0 | rs1) {
+                    const bool qh = rs0 == 0ull;
+                    const int ql = __ffsll((long long)(qh ? rs1 : rs0)) - 1;
+                    if (qh)
+                        rs1 &= rs1 - 1;
+                    else
+                        rs0 &= rs0 - 1;
+                    const unsigned long long kv = qh ? kc1 : kc0;
+                    const unsigned long long kq =
+                        ((unsigned long long)lane_u32((uint32_t)(kv >> 32), ql) << 32) | lane_u32((uint32_t)kv, ql);
+                    const uint32_t own =
+                        (uint32_t)(__popcll(ballot64(kc0 > kq) & L0) + __popcll(ballot64(kc1 > kq) & L1));
+                    if (lane == ql) {
+                        if (qh)
+                            lr1 = own;
+                        else
+                            lr0 = own;
                     }
                 }
-                __syncthreads();
-                lim_ord = sh.mtotal;
-                // the new order, and the coordinates of the positions this
-                // round may still certify
-                for (uint32_t e = P + tid; e < lim_ord; e += kBlock) {
-                    const uint32_t c = tmp[e - P];
-                    ord[e] = c;
-                    if (e < pmax) {
-                        pkx[e] = cx[c];
-                        pky[e] = cy[c];
-                        pkz[e] = cz[c];
-                    }
+                // the picks: the first P live candidates in that order
+                const bool p0 = ((L0 >> lane) & 1ull) && lr0 < P, p1 = ((L1 >> lane) & 1ull) && lr1 < P;
+                if (p0) {
+                    ord[lr0] = cc0;
+                    pkx[lr0] = q0.x;
+                    pky[lr0] = q0.y;
+                    pkz[lr0] = q0.z;
                 }
-                __syncthreads();
-                staged = true;
-                if (lim_ord == P)
-                    break;
+                if (p1) {
+                    ord[lr1] = cc1;
+                    pkx[lr1] = q1.x;
+                    pky[lr1] = q1.y;
+                    pkz[lr1] = q1.z;
+                }
+                if (lane == 0)
+                    sh.npick = P;
+                if (clocks) {
+                    const unsigned long long t = wall_clock64();
+                    tl.sub[2] += t - t_sub;
+                    tl.sub[3] -= t;
+                    tl.fails += nfail;
+                }
             }
-            if (tid == 0)
-                sh.npick = P;
-            // the outputs are written by the idle wavefronts of the next
-            // lookahead (or after the last round), so that waiting for the
-            // stores never delays this workgroup's next publication
-            out_n = P;
-            out_j = (uint32_t)j;
         }
         __syncthreads();
         const int P = (int)sh.npick;
+        // the outputs are written by the idle wavefronts of the next lookahead
+        // (or after the last round), so that waiting for the stores never
+        // delays this workgroup's next publication
+        out_n = (uint32_t)P;
+        out_j = (uint32_t)j;
         if (P == 0) {
             // impossible by construction (the largest bound is attained at round
             // start); kept as a guard so a violated invariant cannot spin forever
@@ -1002,6 +1104,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         if (clocks) {
             const unsigned long long t = wall_clock64();
             tl.ph[2] += t - t_mark;
+            tl.sub[3] += t;  // from the end of the walk (subtracted there)
             t_mark = t;
         }
         j += P;
@@ -1089,6 +1192,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 }
             }
         }
+        if (clocks)
+            tl.sub[8] += wall_clock64() - t_mark;
         __syncthreads();
         if (tid == 0)
             sh.list_n = 0;
@@ -1120,6 +1225,16 @@ __device__ void flush_telemetry(IndexHeader *hdr, const RoundTele &tl, bool cloc
         for (int q = 0; q < 4; ++q)
             atomicAdd(&hdr->tele[kTeleTicksLookahead + q], tl.ph[q]);
         atomicAdd(&hdr->tele[kTeleTicksWait], tl.ph[4]);
+        // the exchange's key forming is its phase minus its polling
+        const unsigned long long sub[8] = {tl.sub[0], tl.sub[1], tl.sub[2], tl.sub[3],
+                                           tl.sub[4], tl.sub[5], tl.sub[6], tl.sub[7] - tl.sub[6]};
+        for (int q = 0; q < 8; ++q)
+            atomicAdd(&hdr->tele[kTeleSub + q], sub[q]);
+        atomicAdd(&hdr->tele[kTeleMergeStats + 0], tl.above);
+        atomicAdd(&hdr->tele[kTeleMergeStats + 1], tl.listed);
+        atomicAdd(&hdr->tele[kTeleMergeStats + 2], tl.fails);
+        atomicAdd(&hdr->tele[kTeleMergeStats + 3], tl.sub[8]);
+        atomicAdd(&hdr->tele[kTeleMergeStats + 4], tl.sub[9]);
     }
 }
 
@@ -1140,7 +1255,8 @@ __device__ __forceinline__ void rounds_single(const RoundArgs &a)
     if (s_status)
         return;
     const bool tele = T && (a.flags & RFPS_F_TELEMETRY) != 0;
-    const bool clocks = tele && blockIdx.x == 0 && tid == 0;
+    const bool timed = T && (a.flags & (RFPS_F_TELEMETRY | RFPS_F_CLOCKS)) != 0;
+    const bool clocks = timed && blockIdx.x == 0 && tid == 0;
     CloudJob job;
     job.tb = 0;
     job.te = hdr->n_tiles;
@@ -1153,8 +1269,8 @@ __device__ __forceinline__ void rounds_single(const RoundArgs &a)
     RoundTele tl;
     const bool ok = sample_cloud<R, Scope::Agent, E, T>(a, job, blockIdx.x, a.G, a.board, epoch, smem, sh, tl,
                                                   (a.flags & RFPS_F_TRACE) != 0 && blockIdx.x == 0, clocks);
-    if (tele && ok) {
-        flush_telemetry(hdr, tl, clocks);
+    if (timed && ok) {
+        flush_telemetry(hdr, tl, clocks);  // the counters stay 0 without RFPS_F_TELEMETRY
         if (blockIdx.x == 0 && tid == 0) {
             atomicAdd(&hdr->tele[0], (unsigned long long)(a.m > 1 ? a.m - 2 : 0));
             atomicAdd(&hdr->tele[1], (unsigned long long)hdr->n_tiles);
@@ -1302,6 +1418,92 @@ RFPS_ROUNDS_KERNEL(k_rfps_rounds_batched_euclid_tele, rounds_batched, true, true
 #undef RFPS_ROUNDS_KERNEL
 
 // ---------------------------------------------------------------------------
+// Exchange floor: G workgroups run `rounds` exchanges with nothing else in a
+// round.  Each publishes W epoch-tagged words and reads every word of every
+// slot until all carry the epoch, with the same agent-scope stores, loads and
+// word-major polling as the sampler's exchange.  Workgroup 0 records the
+// wall-clock ticks of the whole loop in out[0]; an expired wait records
+// RFPS_ERR_TIMEOUT in *status and ends the workgroup.  The launcher clears
+// the slots and out[0..1] first.
+// ---------------------------------------------------------------------------
+constexpr int kProbeMaxWords = 16;
+
+__global__ __launch_bounds__(kBlock) void k_exchange_clear(unsigned long long *board, int words,
+                                                           unsigned long long *out)
+{
+    const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int w = t0; w < words; w += gridDim.x * blockDim.x)
+        board[w] = 0ull;
+    if (t0 < 2)
+        out[t0] = 0ull;
+}
+
+__global__ __launch_bounds__(kBlock) void k_exchange_probe(unsigned long long *board, int G, int W, int rounds,
+                                                           unsigned long long *out, uint32_t *status)
+{
+    const int tid = threadIdx.x, rank = blockIdx.x;
+    const int total = G * W;
+    __shared__ uint32_t s_abort;
+    if (tid == 0)
+        s_abort = 0;
+    __syncthreads();
+    const unsigned long long t0 = wall_clock64();
+    for (uint32_t epoch = 1; epoch <= (uint32_t)rounds; ++epoch) {
+        unsigned long long *sbase = board + (size_t)(epoch & 1u) * G * kMaxSlotWords;
+        if (tid < W)
+            bstore<Scope::Agent>(sbase + (size_t)rank * kMaxSlotWords + tid,
+                                 ((unsigned long long)epoch << 32) | (uint32_t)(rank * W + tid));
+        uint32_t pend = 0;
+#pragma unroll
+        for (int r = 0; r < kProbeMaxWords; ++r)
+            pend |= (tid + kBlock * r < total) ? (1u << r) : 0u;
+        for (uint32_t spin = 0; pend && spin < kSpinLimit; ++spin) {
+            unsigned long long x[kProbeMaxWords];
+#pragma unroll
+            for (int r = 0; r < kProbeMaxWords; ++r) {
+                const int e = tid + kBlock * r;
+                x[r] = ((pend >> r) & 1u) ? bload<Scope::Agent>(sbase + (size_t)(e / W) * kMaxSlotWords + e % W) : 0ull;
+            }
+#pragma unroll
+            for (int r = 0; r < kProbeMaxWords; ++r)
+                if (((pend >> r) & 1u) && (uint32_t)(x[r] >> 32) == epoch)
+                    pend &= ~(1u << r);
+        }
+        if (pend)
+            s_abort = 1;
+        __syncthreads();
+        if (s_abort) {
+            if (tid == 0)
+                set_status(status, RFPS_ERR_TIMEOUT);
+            return;
+        }
+    }
+    if (rank == 0 && tid == 0)
+        out[0] = wall_clock64() - t0;
+}
+
+hipError_t launch_exchange_probe(unsigned long long *board, int G, int W, int rounds, unsigned long long *out,
+                                 uint32_t *status, hipStream_t s)
+{
+    if (G < 1 || G > kMaxGroups || W < 1 || W > kProbeMaxWords || G * W > kBlock * kProbeMaxWords ||
+        2 * G * kMaxSlotWords > kBoardWords || rounds < 1)
+        return hipErrorInvalidValue;
+    k_exchange_clear<<<64, kBlock, 0, s>>>(board, 2 * G * kMaxSlotWords, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    void *args[] = {&board, &G, &W, &rounds, &out, &status};
+    // unused dynamic LDS of more than half a compute unit's keeps one
+    // workgroup per compute unit, as in the sampler
+    const void *fn = reinterpret_cast<const void *>(k_exchange_probe);
+    constexpr int kOnePerCu = 96 * 1024;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kOnePerCu);
+    if (e != hipSuccess)
+        return e;
+    return launch_persistent(fn, G, args, kOnePerCu, s);
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
 static const void *rounds_fn(int R, bool batched, bool euclid, bool tele)
@@ -1377,7 +1579,7 @@ hipError_t launch_rfps_rounds(const IndexView &v, int m, int start, const Sample
     if (e != hipSuccess || m <= 1)
         return e;
     const void *fn = rounds_fn(L.R, false, (L.flags & RFPS_F_SQRT) != 0,
-                               (L.flags & (RFPS_F_TELEMETRY | RFPS_F_TRACE)) != 0);
+                               (L.flags & (RFPS_F_TELEMETRY | RFPS_F_TRACE | RFPS_F_CLOCKS)) != 0);
     if (!fn)
         return hipErrorInvalidValue;
     RoundArgs a = round_args(v, m, start, L, out_idx, out_d2);
@@ -1430,7 +1632,7 @@ hipError_t launch_rfps_rounds_batched(const IndexView &v, const SampleLaunch &L,
     if (e != hipSuccess)
         return e;
     const void *fn = rounds_fn(L.R, true, (L.flags & RFPS_F_SQRT) != 0,
-                               (L.flags & (RFPS_F_TELEMETRY | RFPS_F_TRACE)) != 0);
+                               (L.flags & (RFPS_F_TELEMETRY | RFPS_F_TRACE | RFPS_F_CLOCKS)) != 0);
     if (!fn)
         return hipErrorInvalidValue;
     RoundArgs a = round_args(v, 0, 0, L, out_idx, out_d2);
