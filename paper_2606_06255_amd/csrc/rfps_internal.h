@@ -227,6 +227,11 @@ constexpr int kDppRowMirror = 0x140;
 constexpr int kDppBcast15 = 0x142;
 constexpr int kDppBcast31 = 0x143;
 
+// Lane mask of the lanes where b holds.  A ballot of a single comparison
+// takes the comparison's lane mask as it is, and so do masks combined with &;
+// a ballot of a compound condition first turns it into a value per lane.
+__device__ __forceinline__ unsigned long long ballot64(bool b) { return __builtin_amdgcn_ballot_w64(b); }
+
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
 {
     v = max(v, dpp_u32<kDppQuadSwap1>(v, v));
@@ -254,7 +259,7 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 {
     const uint32_t hi = (uint32_t)(v >> 32);
     const uint32_t mhi = wave_max_u32(hi);
-    const unsigned long long tie = __ballot(hi == mhi);
+    const unsigned long long tie = ballot64(hi == mhi);
     if (__popcll(tie) == 1)  // one lane holds the largest high half: its low half goes with it
         return ((unsigned long long)mhi << 32) |
                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, __ffsll((long long)tie) - 1);

@@ -79,9 +79,6 @@ struct RoundArgs {
 constexpr int kList = 2 * kWave;
 constexpr int kMaxRoundPicks = kList;
 
-// Lane mask of the lanes where b holds.  (A ballot of a single comparison
-// uses the comparison's mask as it is; combining masks with & keeps it so.)
-__device__ __forceinline__ unsigned long long ballot64(bool b) { return __builtin_amdgcn_ballot_w64(b); }
 
 // Value of lane l of v (l uniform).
 __device__ __forceinline__ float lane_f32(float v, int l)
@@ -152,7 +149,7 @@ __device__ __forceinline__ void tile_rekey(int lane, uint32_t lt, uint32_t ls, u
     const uint32_t p = ls + (valid ? lane : 0);
     const unsigned long long key = valid ? pack_key(D[p], po[p]) : 0ull;
     const unsigned long long kmax = wave_max_u64(key);
-    const unsigned long long hit = __ballot(valid && key == kmax);
+    const unsigned long long hit = ballot64(key == kmax) & ballot64(valid);
     if (lane == 0) {
         tkey[lt] = kmax;
         tbest[lt] = ls + (uint32_t)(__ffsll((long long)hit) - 1);
@@ -413,7 +410,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     }
                 }
                 const unsigned long long bk = wave_max_u64(lk);
-                const unsigned long long hit = __ballot(lk == bk && bk != 0);
+                const unsigned long long hit = bk != 0 ? ballot64(lk == bk) : 0ull;
                 if (s == R || bk == 0) {
                     // the bound (or an empty workgroup): no more local candidates
                     if (lane == 0) {
@@ -456,8 +453,9 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 // local update with l_s (pruned against the local thresholds)
                 for (int lt0 = 0; lt0 < ntl; lt0 += kWave) {
                     const int lt = lt0 + lane;
-                    const bool keep = lt < ntl && !(sqdist(tcx[lt], tcy[lt], tcz[lt], lx, ly, lz) >= tthrl[lt]);
-                    unsigned long long m = __ballot(keep);
+                    const int li = lt < ntl ? lt : 0;
+                    unsigned long long m =
+                        ballot64(!(sqdist(tcx[li], tcy[li], tcz[li], lx, ly, lz) >= tthrl[li])) & ballot64(lt < ntl);
                     while (m) {
                         const int t = lt0 + (__ffsll((long long)m) - 1);
                         m &= m - 1;
@@ -828,59 +826,72 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             const unsigned long long k1 =
                 ((unsigned long long)__float_as_uint(q1.w) << 32) | sh.lkl[two ? lane + kWave : lane];
             {
-                const bool rep = sh.rep != 0;
-                auto one = [&](uint32_t i, uint32_t &s0l, uint32_t &s0h, uint32_t &s1l, uint32_t &s1h, uint32_t &rk) {
-                    const float4 qi = sh.lq[i];
-                    const unsigned long long ki = ((unsigned long long)__float_as_uint(qi.w) << 32) | sh.lkl[i];
-                    const float d0 = sqdist(qi.x, qi.y, qi.z, q0.x, q0.y, q0.z);
-                    bool b0 = d0 < qi.w;
-                    if (euclid && b0)
-                        b0 = sqrt_class_top(d0) < qi.w;
-                    const unsigned long long g0 = ballot64(k0 > ki) & v0;
-                    const unsigned long long m0 = ballot64(b0) & g0;
-                    rk = (uint32_t)__popcll(g0);
-                    unsigned long long m1 = 0;
-                    if (two) {
-                        const float d1 = sqdist(qi.x, qi.y, qi.z, q1.x, q1.y, q1.z);
-                        bool b1 = d1 < qi.w;
-                        if (euclid && b1)
-                            b1 = sqrt_class_top(d1) < qi.w;
-                        const unsigned long long g1 = ballot64(k1 > ki) & v1;
-                        m1 = ballot64(b1) & g1;
-                        rk += (uint32_t)__popcll(g1);
-                    }
-                    if (rep) {
-                        // equal keys listed before i
-                        const unsigned long long below_i =
-                            (i & (kWave - 1)) ? ~0ull >> (kWave - (i & (kWave - 1))) : 0ull;
-                        const unsigned long long e0 = ballot64(k0 == ki) & v0 & (i >= (uint32_t)kWave ? ~0ull : below_i);
-                        rk += (uint32_t)__popcll(e0);
-                        if (two) {
-                            const unsigned long long e1 =
-                                ballot64(k1 == ki) & v1 & (i >= (uint32_t)kWave ? below_i : 0ull);
-                            rk += (uint32_t)__popcll(e1);
-                        }
-                    }
-                    s0l = (uint32_t)m0;
-                    s0h = (uint32_t)(m0 >> 32);
-                    s1l = (uint32_t)m1;
-                    s1h = (uint32_t)(m1 >> 32);
-                };
                 uint32_t r0l = 0, r0h = 0, r1l = 0, r1h = 0, rrk = 0;
-                int t = 0;
-                for (uint32_t i = (uint32_t)wave; i < W; i += 2 * kWavesPerBlock, t += 2) {
-                    // two independent candidates per pass (the second may lie
-                    // past the list: its results are not kept)
-                    const uint32_t i2 = i + kWavesPerBlock < W ? i + kWavesPerBlock : i;
-                    uint32_t a0l, a0h, a1l, a1h, ark, b0l, b0h, b1l, b1h, brk;
-                    one(i, a0l, a0h, a1l, a1h, ark);
-                    one(i2, b0l, b0h, b1l, b1h, brk);
-                    const bool ma = lane == t, mb = lane == t + 1;
-                    r0l = ma ? a0l : mb ? b0l : r0l;
-                    r0h = ma ? a0h : mb ? b0h : r0h;
-                    r1l = ma ? a1l : mb ? b1l : r1l;
-                    r1h = ma ? a1h : mb ? b1h : r1h;
-                    rrk = ma ? ark : mb ? brk : rrk;
+                // both candidates of a pass and both chunks are straight-line
+                // code (the second chunk is a compile-time case), so their
+                // independent chains interleave
+                auto pass = [&](auto two_c) {
+                    constexpr bool TWO = decltype(two_c)::value;
+                    int t = 0;
+                    for (uint32_t i = (uint32_t)wave; i < W; i += 2 * kWavesPerBlock, t += 2) {
+                        // the second candidate may lie past the list: its
+                        // results are not kept
+                        const uint32_t i2 = i + kWavesPerBlock < W ? i + kWavesPerBlock : i;
+                        const float4 qa = sh.lq[i], qb = sh.lq[i2];
+                        const unsigned long long ka = ((unsigned long long)__float_as_uint(qa.w) << 32) | sh.lkl[i];
+                        const unsigned long long kb = ((unsigned long long)__float_as_uint(qb.w) << 32) | sh.lkl[i2];
+                        const float da0 = sqdist(qa.x, qa.y, qa.z, q0.x, q0.y, q0.z);
+                        const float db0 = sqdist(qb.x, qb.y, qb.z, q0.x, q0.y, q0.z);
+                        const unsigned long long ga0 = ballot64(k0 > ka) & v0, gb0 = ballot64(k0 > kb) & v0;
+                        bool ba0 = da0 < qa.w, bb0 = db0 < qb.w;
+                        if (euclid) {
+                            ba0 = ba0 && sqrt_class_top(da0) < qa.w;
+                            bb0 = bb0 && sqrt_class_top(db0) < qb.w;
+                        }
+                        const unsigned long long ma0 = ballot64(ba0) & ga0, mb0 = ballot64(bb0) & gb0;
+                        uint32_t rka = (uint32_t)__popcll(ga0), rkb = (uint32_t)__popcll(gb0);
+                        unsigned long long ma1 = 0, mb1 = 0;
+                        if constexpr (TWO) {
+                            const float da1 = sqdist(qa.x, qa.y, qa.z, q1.x, q1.y, q1.z);
+                            const float db1 = sqdist(qb.x, qb.y, qb.z, q1.x, q1.y, q1.z);
+                            const unsigned long long ga1 = ballot64(k1 > ka) & v1, gb1 = ballot64(k1 > kb) & v1;
+                            bool ba1 = da1 < qa.w, bb1 = db1 < qb.w;
+                            if (euclid) {
+                                ba1 = ba1 && sqrt_class_top(da1) < qa.w;
+                                bb1 = bb1 && sqrt_class_top(db1) < qb.w;
+                            }
+                            ma1 = ballot64(ba1) & ga1;
+                            mb1 = ballot64(bb1) & gb1;
+                            rka += (uint32_t)__popcll(ga1);
+                            rkb += (uint32_t)__popcll(gb1);
+                        }
+                        // lane t keeps the results of this wavefront's t-th candidate
+                        const bool sa = lane == t, sb = lane == t + 1;
+                        r0l = sa ? (uint32_t)ma0 : sb ? (uint32_t)mb0 : r0l;
+                        r0h = sa ? (uint32_t)(ma0 >> 32) : sb ? (uint32_t)(mb0 >> 32) : r0h;
+                        r1l = sa ? (uint32_t)ma1 : sb ? (uint32_t)mb1 : r1l;
+                        r1h = sa ? (uint32_t)(ma1 >> 32) : sb ? (uint32_t)(mb1 >> 32) : r1h;
+                        rrk = sa ? rka : sb ? rkb : rrk;
+                    }
+                };
+                if (two)
+                    pass(std::true_type());
+                else
+                    pass(std::false_type());
+                if (sh.rep) {
+                    // equal keys (repeats of one point): those listed before a
+                    // candidate also rank above it
+                    int t = 0;
+                    for (uint32_t i = (uint32_t)wave; i < W; i += kWavesPerBlock, ++t) {
+                        const float4 qi = sh.lq[i];
+                        const unsigned long long ki = ((unsigned long long)__float_as_uint(qi.w) << 32) | sh.lkl[i];
+                        const uint32_t il = i & (kWave - 1);
+                        const unsigned long long before = il ? ~0ull >> (kWave - il) : 0ull;
+                        const unsigned long long e0 = ballot64(k0 == ki) & v0 & (i >= (uint32_t)kWave ? ~0ull : before);
+                        const unsigned long long e1 = ballot64(k1 == ki) & v1 & (i >= (uint32_t)kWave ? before : 0ull);
+                        if (lane == t)
+                            rrk += (uint32_t)(__popcll(e0) + __popcll(e1));
+                    }
                 }
                 // lane t holds the results of this wavefront's t-th candidate
                 const uint32_t i = (uint32_t)wave + (uint32_t)kWavesPerBlock * (uint32_t)lane;
@@ -1139,7 +1150,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     const bool tin = lt < ntl;
                     const int li = tin ? lt : 0;
                     const bool keep = !(sqdist(qx[v], qy[v], qz[v], sx, sy, sz) >= qt[v]);
-                    m[v] = tin ? __ballot(keep) & kmask : 0ull;
+                    m[v] = tin ? ballot64(keep) & kmask : 0ull;
                     if (tele && lane == 0 && tin) {
                         const unsigned long long nh = (unsigned long long)__popcll(m[v]);
                         tl.tests += nk;
