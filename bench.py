@@ -37,7 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # of CDNA3, taken as the floor for gfx950)
 LDS_PEAK_GBS = 256 * 128 * 2.4
 PHASES = ("lookahead", "lookahead_copy", "lookahead_select", "exchange", "exchange_poll", "exchange_keys",
-          "wait", "merge", "merge_list", "merge_rank", "merge_walk", "merge_picks", "apply", "apply_loop")
+          "wait", "merge", "merge_list", "merge_rank", "merge_walk", "merge_picks", "apply", "apply_loop",
+          "apply_update")
 WORKLOADS = {
     "dense_lidar": "dense LiDAR-like cloud, 128 beams x 8192 azimuth, N=1,048,576, M=65,536",
     "room": "indoor room-like cloud, N=80,000, M=20,000",
@@ -219,7 +220,8 @@ def main():
     phases["lookahead_update"] = phases["lookahead"] - phases["lookahead_copy"] - phases["lookahead_select"]
     phases["round"] = sum(phases[k] for k in ("lookahead", "exchange", "merge", "apply"))
     merge_stats = {"above": clk["merge_above"] / nr, "listed": clk["merge_listed"] / nr,
-                   "failures": clk["merge_failures"] / nr}
+                   "failures": clk["merge_failures"] / nr, "wg0_apply_pairs": clk["apply_pairs"] / nr,
+                   "wg0_apply_rekeys": clk["apply_rekeys"] / nr}
     # latency floor of one exchange round: bare exchanges of the sampler's
     # slot size among the same workgroups (nothing else in the round)
     G_used = args.groups or 0

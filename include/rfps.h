@@ -160,7 +160,12 @@ typedef struct rfps_telemetry {
      * local candidate and its runner-up, without the local updates) */
     int64_t ticks_apply_loop;
     int64_t ticks_lookahead_select;
-    int64_t reserved2[3];
+    /* workgroup 0's first wavefront in the apply phase: clocks of its point
+     * updates (tiles some pick reaches), the tile-pick pairs it updated and
+     * the tiles it re-keyed */
+    int64_t ticks_apply_update;
+    int64_t apply_pairs;
+    int64_t apply_rekeys;
 } rfps_telemetry;
 
 /* Shape of a built index, read back by rfps_read_index_info(). */

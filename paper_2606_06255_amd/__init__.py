@@ -50,8 +50,8 @@ class rfps_telemetry(ctypes.Structure):
         "ticks_merge", "ticks_apply", "tick_hz", "ticks_wait", "reserved",
         "ticks_merge_list", "ticks_merge_rank", "ticks_merge_walk", "ticks_merge_picks", "ticks_lookahead_copy",
         "ticks_lookahead_steps", "ticks_exchange_poll", "ticks_exchange_keys", "merge_above", "merge_listed",
-        "merge_failures", "ticks_apply_loop", "ticks_lookahead_select", "reserved2_0", "reserved2_1",
-        "reserved2_2")]
+        "merge_failures", "ticks_apply_loop", "ticks_lookahead_select", "ticks_apply_update", "apply_pairs",
+        "apply_rekeys")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_ if not k.startswith("reserved")}

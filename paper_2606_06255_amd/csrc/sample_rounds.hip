@@ -140,7 +140,9 @@ __global__ __launch_bounds__(kBlock) void k_rounds_plan(IndexHeader *hdr, const 
 }
 
 // One wavefront recomputes the key, best point and threshold of tile lt from
-// the distances in D (all lanes of the wave must call it).
+// the distances in D (all lanes of the wave must call it).  The threshold
+// goes to tthr[lt * TS].
+template <int TS>
 __device__ __forceinline__ void tile_rekey(int lane, uint32_t lt, uint32_t ls, uint32_t cnt, const float *D,
                                            const uint32_t *po, const float *trad, unsigned long long *tkey,
                                            uint32_t *tbest, float *tthr)
@@ -153,7 +155,7 @@ __device__ __forceinline__ void tile_rekey(int lane, uint32_t lt, uint32_t ls, u
     if (lane == 0) {
         tkey[lt] = kmax;
         tbest[lt] = ls + (uint32_t)(__ffsll((long long)hit) - 1);
-        tthr[lt] = prune_threshold(trad[lt], key_d2(kmax));
+        tthr[lt * TS] = prune_threshold(trad[lt], key_d2(kmax));
     }
 }
 
@@ -207,7 +209,8 @@ struct RoundTele {
     unsigned long long ph[5] = {0, 0, 0, 0, 0};  // lookahead, exchange, merge, apply, exchange wait
     // finer clocks: merge list / rank / walk / picks, lookahead copy / steps,
     // exchange poll / keys; and the merge's list lengths and failures
-    unsigned long long sub[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // + apply tile loop, lookahead selects
+    unsigned long long sub[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // + apply loop, lookahead selects, apply updates
+    unsigned long long apairs = 0, arekeys = 0;  // wavefront 0's apply: tile-pick pairs updated, tiles re-keyed
     unsigned long long above = 0, listed = 0, fails = 0;
     unsigned long long rounds = 0;
 };
@@ -255,12 +258,17 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
     float *pkx = reinterpret_cast<float *>(skey);
     float *pky = pkx + kMaxRoundPicks;
     float *pkz = pky + kMaxRoundPicks;
-    float *tcx = reinterpret_cast<float *>(skey) + merge_words(G, R);
-    float *tcy = tcx + ntl;
-    float *tcz = tcy + ntl;
-    float *trad = tcz + ntl;
-    float *tthr = trad + ntl;
-    float *tthrl = tthr + ntl;
+    // tile spheres with their pruning thresholds: (centre, threshold), one
+    // 16-byte load per tile test
+    // (aligned by offset from the LDS base, so that the compiler still sees
+    // an LDS pointer)
+    const size_t tsph_off =
+        ((size_t)(reinterpret_cast<unsigned char *>(reinterpret_cast<float *>(skey) + merge_words(G, R)) - smem) + 15) &
+        ~(size_t)15;
+    float4 *tsph = reinterpret_cast<float4 *>(smem + tsph_off);
+    float *tthr = reinterpret_cast<float *>(tsph) + 3;  // with stride 4
+    float *trad = reinterpret_cast<float *>(tsph + ntl);
+    float *tthrl = trad + ntl;
     uint32_t *tmeta = reinterpret_cast<uint32_t *>(tthrl + ntl);
     uint32_t *tbest = tmeta + ntl;
     uint32_t *tbestl = tbest + ntl;
@@ -300,9 +308,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         const size_t t = job.tb + rank + (size_t)lt * G;
         const uint32_t c = a.tcnt[t];
         tmeta[lt] = off | (c << 16);
-        tcx[lt] = a.tcx[t];
-        tcy[lt] = a.tcy[t];
-        tcz[lt] = a.tcz[t];
+        tsph[lt] = make_float4(a.tcx[t], a.tcy[t], a.tcz[t], 0.0f);
         trad[lt] = a.trad[t];
         off += c;
     }
@@ -343,7 +349,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 pd[p] = euclid ? sqrt_class_top(d0) : d0;
                 po[p] = a.orig[i] - job.point_base;
             }
-            tile_rekey(lane, lt, ls, c, pd, po, trad, tkey, tbest, tthr);
+            tile_rekey<4>(lane, lt, ls, c, pd, po, trad, tkey, tbest, tthr);
         }
         if (tid == 0) {
             sh.list_n = 0;
@@ -384,7 +390,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         if (wave == 0) {
             for (int lt = lane; lt < ntl; lt += kWave) {
                 tkeyl[lt] = tkey[lt];
-                tthrl[lt] = tthr[lt];
+                tthrl[lt] = tsph[lt].w;
                 tbestl[lt] = tbest[lt];
                 tflag[lt] = 0;
             }
@@ -399,15 +405,15 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     tl.sub[9] -= wall_clock64();
                 unsigned long long lk = 0, lk2 = 0;  // the lane's two largest tile keys
                 uint32_t lt_best = 0;
-                for (int lt = lane; lt < ntl; lt += kWave) {
-                    const unsigned long long k = tkeyl[lt];
-                    if (k > lk) {
-                        lk2 = lk;
-                        lk = k;
-                        lt_best = (uint32_t)lt;
-                    } else if (k > lk2) {
-                        lk2 = k;
-                    }
+                // same trip count on every lane, loads clamped: no branches
+                for (int lt0 = 0; lt0 < ntl; lt0 += kWave) {
+                    const int lt = lt0 + lane;
+                    const unsigned long long kr = tkeyl[lt < ntl ? lt : 0];
+                    const unsigned long long k = lt < ntl ? kr : 0ull;
+                    const bool top = k > lk;
+                    lk2 = top ? lk : umax64(lk2, k);
+                    lt_best = top ? (uint32_t)lt : lt_best;
+                    lk = top ? k : lk;
                 }
                 const unsigned long long bk = wave_max_u64(lk);
                 const unsigned long long hit = bk != 0 ? ballot64(lk == bk) : 0ull;
@@ -436,7 +442,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     const uint32_t ls = meta & 0xffffu, cnt = meta >> 16;
                     const bool valid = (uint32_t)lane < cnt;
                     const uint32_t pp = ls + (valid ? lane : 0);
-                    const float dl = tflag[bt] ? pdl[pp] : pd[pp];
+                    const float dpl = pdl[pp], dpt = pd[pp];
+                    const float dl = tflag[bt] ? dpl : dpt;
                     const unsigned long long k = valid ? pack_key(dl, po[pp]) : 0ull;
                     ru = umax64(ru, wave_max_u64(k == bk ? 0ull : k));
                 }
@@ -455,7 +462,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     const int lt = lt0 + lane;
                     const int li = lt < ntl ? lt : 0;
                     unsigned long long m =
-                        ballot64(!(sqdist(tcx[li], tcy[li], tcz[li], lx, ly, lz) >= tthrl[li])) & ballot64(lt < ntl);
+                        ballot64(!(sqdist(tsph[li].x, tsph[li].y, tsph[li].z, lx, ly, lz) >= tthrl[li])) &
+                        ballot64(lt < ntl);
                     while (m) {
                         const int t = lt0 + (__ffsll((long long)m) - 1);
                         m &= m - 1;
@@ -486,7 +494,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                         if (lane == 0)
                             tflag[t] = 1;
                         if (__ballot(upd))
-                            tile_rekey(lane, t, ls, cnt, pdl, po, trad, tkeyl, tbestl, tthrl);
+                            tile_rekey<1>(lane, t, ls, cnt, pdl, po, trad, tkeyl, tbestl, tthrl);
                     }
                 }
             }
@@ -1128,9 +1136,10 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         // uses its current threshold (only its own update can lower it); the
         // picks that survive update the tile's points, in pick order.
         for (int kb = 0; kb < P; kb += kWave) {
-            const int k = kb + lane;
-            const bool kin = k < P;
-            const float sx = kin ? pkx[k] : 0.0f, sy = kin ? pky[k] : 0.0f, sz = kin ? pkz[k] : 0.0f;
+            // every load below is unconditional (indices clamped, results
+            // masked), so the common path has no branches
+            const int k = kb + lane < P ? kb + lane : kb;
+            const float sx = pkx[k], sy = pky[k], sz = pkz[k];
             const unsigned long long nk = (unsigned long long)min(kWave, P - kb);
             const unsigned long long kmask = nk == kWave ? ~0ull : ((1ull << nk) - 1ull);
             for (int lt0 = 4 * wave; lt0 < ntl; lt0 += 4 * kWavesPerBlock) {
@@ -1139,10 +1148,11 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int li = lt0 + v < ntl ? lt0 + v : lt0;
-                    qx[v] = tcx[li];
-                    qy[v] = tcy[li];
-                    qz[v] = tcz[li];
-                    qt[v] = tthr[li];
+                    const float4 sp = tsph[li];
+                    qx[v] = sp.x;
+                    qy[v] = sp.y;
+                    qz[v] = sp.z;
+                    qt[v] = sp.w;
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
@@ -1150,13 +1160,18 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     const bool tin = lt < ntl;
                     const int li = tin ? lt : 0;
                     const bool keep = !(sqdist(qx[v], qy[v], qz[v], sx, sy, sz) >= qt[v]);
-                    m[v] = tin ? ballot64(keep) & kmask : 0ull;
+                    m[v] = ballot64(keep) & (tin ? kmask : 0ull);
                     if (tele && lane == 0 && tin) {
                         const unsigned long long nh = (unsigned long long)__popcll(m[v]);
                         tl.tests += nk;
                         tl.pruned += nk - nh;
                         tl.visited += nh * (tmeta[li] >> 16);
                     }
+                }
+                unsigned long long t_upd = 0;
+                if (clocks && (m[0] | m[1] | m[2] | m[3])) {
+                    t_upd = wall_clock64();
+                    tl.apairs += (unsigned long long)(__popcll(m[0]) + __popcll(m[1]) + __popcll(m[2]) + __popcll(m[3]));
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
@@ -1199,8 +1214,12 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                         tl.resync += um != 0;
                     }
                     if (um)
-                        tile_rekey(lane, lt, ls, cnt, pd, po, trad, tkey, tbest, tthr);
+                        tile_rekey<4>(lane, lt, ls, cnt, pd, po, trad, tkey, tbest, tthr);
+                    if (clocks && um)
+                        ++tl.arekeys;
                 }
+                if (clocks && t_upd)
+                    tl.sub[10] += wall_clock64() - t_upd;
             }
         }
         if (clocks)
@@ -1246,6 +1265,9 @@ __device__ void flush_telemetry(IndexHeader *hdr, const RoundTele &tl, bool cloc
         atomicAdd(&hdr->tele[kTeleMergeStats + 2], tl.fails);
         atomicAdd(&hdr->tele[kTeleMergeStats + 3], tl.sub[8]);
         atomicAdd(&hdr->tele[kTeleMergeStats + 4], tl.sub[9]);
+        atomicAdd(&hdr->tele[kTeleMergeStats + 5], tl.sub[10]);
+        atomicAdd(&hdr->tele[kTeleMergeStats + 6], tl.apairs);
+        atomicAdd(&hdr->tele[kTeleMergeStats + 7], tl.arekeys);
     }
 }
 

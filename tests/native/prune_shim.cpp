@@ -5,7 +5,7 @@
 
 extern "C" float shim_prune_threshold(float R, float dv) { return rfps::prune_threshold(R, dv); }
 
-extern "C" float shim_prune_threshold_with(float R, float dv, double inner, double outer, double step)
+extern "C" float shim_prune_threshold_with(float R, float dv, float inner, float outer)
 {
-    return rfps::prune_threshold_with(R, dv, inner, outer, step);
+    return rfps::prune_threshold_with(R, dv, inner, outer);
 }

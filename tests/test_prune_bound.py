@@ -28,10 +28,10 @@ def shim(tmp_path_factory):
     subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
                     "-Wall", "-o", out, os.path.join(HERE, "native", "prune_shim.cpp")], check=True)
     L = ctypes.CDLL(out)
-    f, d = ctypes.c_float, ctypes.c_double
+    f = ctypes.c_float
     L.shim_prune_threshold.argtypes = [f, f]
     L.shim_prune_threshold.restype = f
-    L.shim_prune_threshold_with.argtypes = [f, f, d, d, d]
+    L.shim_prune_threshold_with.argtypes = [f, f, f, f]
     L.shim_prune_threshold_with.restype = f
     return L
 
@@ -194,7 +194,7 @@ def test_zero_margin_variant_is_caught(shim):
     real-arithmetic proof, rounded up) skips tiles whose members would
     still be updated: the checks above must reject it."""
     cs = cases()
-    zero = lambda R, dv: shim.shim_prune_threshold_with(R, dv, 1.0, 1.0, 1.0)  # noqa: E731
+    zero = lambda R, dv: shim.shim_prune_threshold_with(R, dv, 1.0, 1.0)  # noqa: E731
     skips, bad_exact, bad_member = violations(zero, cs)
     assert bad_exact > 0
     assert bad_member > 0
