@@ -260,7 +260,7 @@ rfps_status rfps_read_telemetry(const rfps_index *index, void *stream, rfps_tele
 /*
  * Latency floor of the sampler's exchange (measurement only): `groups`
  * workgroups (0 = one per compute unit, at most 256) run `rounds` exchanges
- * of `words` (1..16) epoch-tagged 64-bit words each per workgroup, with
+ * of `words` (1..64) epoch-tagged 64-bit words each per workgroup, with
  * nothing else in a round, through the same agent-scope stores, loads and
  * polling as the multi-pick sampler (which publishes 6 * lookahead + 2
  * words).  Uses the index's exchange board and trace buffer as scratch (the

@@ -424,7 +424,7 @@ rfps_status rfps_probe_exchange(const rfps_index *index, int32_t groups, int32_t
     rfps_status st = check_index(index);
     if (st != RFPS_OK)
         return st;
-    if (!us_per_round || words < 1 || words > 16 || rounds < 1 || rounds > (1 << 20) || groups < 0)
+    if (!us_per_round || words < 1 || words > kMaxSlotWords || rounds < 1 || rounds > (1 << 20) || groups < 0)
         return RFPS_ERR_INVALID_ARG;
     const DeviceInfo *d = device_info();
     if (!d)

@@ -361,20 +361,6 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
     unsigned long long t_mark = 0;
     int j = 1;
     uint32_t round = 0;
-    uint32_t out_n = 0, out_j = 0;  // selections of the last merge not yet written out
-    // writes them (rank 0 only) from threads [t0, kBlock); the merge's order,
-    // indices and distances stay in LDS until the next exchange
-    auto write_out = [&](int t0) {
-        if (rank == 0) {
-            const uint32_t *mord = reinterpret_cast<const uint32_t *>(bkey);
-            for (uint32_t k = (uint32_t)(tid - t0); k < out_n; k += (uint32_t)(kBlock - t0)) {
-                const uint32_t c = mord[k];
-                job.out_idx[out_j + k] = (int32_t)corig[c];
-                if (job.out_d2)
-                    job.out_d2[out_j + k] = cld[c];
-            }
-        }
-    };
     while (j < job.m) {
         ++round;
         ++epoch;
@@ -385,8 +371,6 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         // inside it and its LDS operations complete in order, so the steps
         // need no workgroup barrier.  Lanes take tiles for the arg max and the
         // sphere tests; a tile that the test keeps is updated by all lanes.
-        if (wave != 0 && out_n)
-            write_out(kWave);
         if (wave == 0) {
             for (int lt = lane; lt < ntl; lt += kWave) {
                 tkeyl[lt] = tkey[lt];
@@ -500,7 +484,6 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             }
         }
         __syncthreads();
-        out_n = 0;
         if (clocks) {
             const unsigned long long t = wall_clock64();
             tl.ph[0] += t - t_mark;
@@ -1078,19 +1061,31 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                             lr0 = own;
                     }
                 }
-                // the picks: the first P live candidates in that order
+                // the picks: the first P live candidates in that order.  Their
+                // coordinates go to the apply phase; rank 0 writes the
+                // outputs (original index and distance from the listed key)
+                // straight away, long before this wavefront next waits on
+                // device memory (in the next exchange)
                 const bool p0 = ((L0 >> lane) & 1ull) && lr0 < P, p1 = ((L1 >> lane) & 1ull) && lr1 < P;
                 if (p0) {
-                    ord[lr0] = cc0;
                     pkx[lr0] = q0.x;
                     pky[lr0] = q0.y;
                     pkz[lr0] = q0.z;
+                    if (rank == 0) {
+                        job.out_idx[j + (int)lr0] = (int32_t)~(uint32_t)kc0;
+                        if (job.out_d2)
+                            job.out_d2[j + (int)lr0] = __uint_as_float((uint32_t)(kc0 >> 32));
+                    }
                 }
                 if (p1) {
-                    ord[lr1] = cc1;
                     pkx[lr1] = q1.x;
                     pky[lr1] = q1.y;
                     pkz[lr1] = q1.z;
+                    if (rank == 0) {
+                        job.out_idx[j + (int)lr1] = (int32_t)~(uint32_t)kc1;
+                        if (job.out_d2)
+                            job.out_d2[j + (int)lr1] = __uint_as_float((uint32_t)(kc1 >> 32));
+                    }
                 }
                 if (lane == 0)
                     sh.npick = P;
@@ -1104,11 +1099,6 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         }
         __syncthreads();
         const int P = (int)sh.npick;
-        // the outputs are written by the idle wavefronts of the next lookahead
-        // (or after the last round), so that waiting for the stores never
-        // delays this workgroup's next publication
-        out_n = (uint32_t)P;
-        out_j = (uint32_t)j;
         if (P == 0) {
             // impossible by construction (the largest bound is attained at round
             // start); kept as a guard so a violated invariant cannot spin forever
@@ -1131,96 +1121,111 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             break;
 
         // =============== A: apply the round's picks to the true state ===============
-        // Lanes take picks (64 at a time), wavefronts take tiles, four at a
-        // time so that their sphere data is in flight together.  A tile's test
-        // uses its current threshold (only its own update can lower it); the
-        // picks that survive update the tile's points, in pick order.
-        for (int kb = 0; kb < P; kb += kWave) {
-            // every load below is unconditional (indices clamped, results
-            // masked), so the common path has no branches
-            const int k = kb + lane < P ? kb + lane : kb;
-            const float sx = pkx[k], sy = pky[k], sz = pkz[k];
-            const unsigned long long nk = (unsigned long long)min(kWave, P - kb);
-            const unsigned long long kmask = nk == kWave ? ~0ull : ((1ull << nk) - 1ull);
-            for (int lt0 = 4 * wave; lt0 < ntl; lt0 += 4 * kWavesPerBlock) {
-                unsigned long long m[4];
-                float qx[4], qy[4], qz[4], qt[4];
+        // Lanes take picks k and k + 64 (the second set only when the round
+        // has more than 64), wavefronts take tiles, four at a time so that
+        // their sphere data is in flight together.  A tile's test uses its
+        // current threshold (only its own update can lower it); the picks
+        // that survive update the tile's points (the minimum over picks does
+        // not depend on their order).  Every load of the tests is
+        // unconditional (indices clamped, results masked), so their path has
+        // no branches.
+        {
+            const int ka = lane < P ? lane : 0, kc = lane + kWave < P ? lane + kWave : 0;
+            const float sax = pkx[ka], say = pky[ka], saz = pkz[ka];
+            const float scx = pkx[kc], scy = pky[kc], scz = pkz[kc];
+            const unsigned long long kma = P >= kWave ? ~0ull : ((1ull << P) - 1ull);
+            const unsigned long long kmc =
+                P >= 2 * kWave ? ~0ull : P > kWave ? ((1ull << (P - kWave)) - 1ull) : 0ull;
+            auto pass = [&](auto two_c) {
+                constexpr bool TWO = decltype(two_c)::value;
+                for (int lt0 = 4 * wave; lt0 < ntl; lt0 += 4 * kWavesPerBlock) {
+                    unsigned long long ma[4], mc[4];
+                    float qx[4], qy[4], qz[4], qt[4];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int li = lt0 + v < ntl ? lt0 + v : lt0;
-                    const float4 sp = tsph[li];
-                    qx[v] = sp.x;
-                    qy[v] = sp.y;
-                    qz[v] = sp.z;
-                    qt[v] = sp.w;
-                }
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int lt = lt0 + v;
-                    const bool tin = lt < ntl;
-                    const int li = tin ? lt : 0;
-                    const bool keep = !(sqdist(qx[v], qy[v], qz[v], sx, sy, sz) >= qt[v]);
-                    m[v] = ballot64(keep) & (tin ? kmask : 0ull);
-                    if (tele && lane == 0 && tin) {
-                        const unsigned long long nh = (unsigned long long)__popcll(m[v]);
-                        tl.tests += nk;
-                        tl.pruned += nk - nh;
-                        tl.visited += nh * (tmeta[li] >> 16);
+                    for (int v = 0; v < 4; ++v) {
+                        const int li = lt0 + v < ntl ? lt0 + v : lt0;
+                        const float4 sp = tsph[li];
+                        qx[v] = sp.x;
+                        qy[v] = sp.y;
+                        qz[v] = sp.z;
+                        qt[v] = sp.w;
                     }
-                }
-                unsigned long long t_upd = 0;
-                if (clocks && (m[0] | m[1] | m[2] | m[3])) {
-                    t_upd = wall_clock64();
-                    tl.apairs += (unsigned long long)(__popcll(m[0]) + __popcll(m[1]) + __popcll(m[2]) + __popcll(m[3]));
-                }
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    unsigned long long mask = m[v];
-                    if (!mask)
-                        continue;
-                    const int lt = lt0 + v;
-                    const uint32_t meta = tmeta[lt];
-                    const uint32_t ls = meta & 0xffffu, cnt = meta >> 16;
-                    const bool valid = (uint32_t)lane < cnt;
-                    const uint32_t pp = ls + (valid ? lane : 0);
-                    const float x = px[pp], y = py[pp], z = pz[pp];
-                    float d = pd[pp];
-                    bool changed = false;
-                    while (mask) {
-                        const int kk = kb + (__ffsll((long long)mask) - 1);
-                        mask &= mask - 1;
-                        const float qx = pkx[kk], qy = pky[kk], qz = pkz[kk];
-                        if (valid) {
-                            const float dx = x - qx, dy = y - qy, dz = z - qz;
-                            const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-                            const bool skip = use_skip && (xx >= d || yy >= d || zz >= d);
-                            const float s2 = xx + yy;
-                            float t = s2 + zz;
-                            if (euclid && !skip && t < d)
-                                t = sqrt_class_top(t);
-                            if (!skip && t < d) {
-                                d = t;
-                                changed = true;
-                            }
-                            if (tele)
-                                tl.skipped += skip;
+                    for (int v = 0; v < 4; ++v) {
+                        const int lt = lt0 + v;
+                        const bool tin = lt < ntl;
+                        ma[v] = ballot64(!(sqdist(qx[v], qy[v], qz[v], sax, say, saz) >= qt[v])) & (tin ? kma : 0ull);
+                        mc[v] = TWO ? ballot64(!(sqdist(qx[v], qy[v], qz[v], scx, scy, scz) >= qt[v])) &
+                                          (tin ? kmc : 0ull)
+                                    : 0ull;
+                        if (tele && lane == 0 && tin) {
+                            const unsigned long long nh = (unsigned long long)(__popcll(ma[v]) + __popcll(mc[v]));
+                            tl.tests += (unsigned long long)P;
+                            tl.pruned += (unsigned long long)P - nh;
+                            tl.visited += nh * (tmeta[lt] >> 16);
                         }
                     }
-                    if (changed)
-                        pd[pp] = d;
-                    const unsigned long long um = __ballot(changed);
-                    if (tele && lane == 0) {
-                        tl.updated += (unsigned long long)__popcll(um);
-                        tl.resync += um != 0;
+                    unsigned long long t_upd = 0;
+                    if (clocks && (ma[0] | ma[1] | ma[2] | ma[3] | mc[0] | mc[1] | mc[2] | mc[3])) {
+                        t_upd = wall_clock64();
+                        for (int v = 0; v < 4; ++v)
+                            tl.apairs += (unsigned long long)(__popcll(ma[v]) + __popcll(mc[v]));
                     }
-                    if (um)
-                        tile_rekey<4>(lane, lt, ls, cnt, pd, po, trad, tkey, tbest, tthr);
-                    if (clocks && um)
-                        ++tl.arekeys;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        if (!(ma[v] | mc[v]))
+                            continue;
+                        const int lt = lt0 + v;
+                        const uint32_t meta = tmeta[lt];
+                        const uint32_t ls = meta & 0xffffu, cnt = meta >> 16;
+                        const bool valid = (uint32_t)lane < cnt;
+                        const uint32_t pp = ls + (valid ? lane : 0);
+                        const float x = px[pp], y = py[pp], z = pz[pp];
+                        float d = pd[pp];
+                        bool changed = false;
+                        for (int h = 0; h < (TWO ? 2 : 1); ++h) {
+                            unsigned long long mask = h ? mc[v] : ma[v];
+                            while (mask) {
+                                const int kk = (h ? kWave : 0) + (__ffsll((long long)mask) - 1);
+                                mask &= mask - 1;
+                                const float qx = pkx[kk], qy = pky[kk], qz = pkz[kk];
+                                if (valid) {
+                                    const float dx = x - qx, dy = y - qy, dz = z - qz;
+                                    const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+                                    const bool skip = use_skip && (xx >= d || yy >= d || zz >= d);
+                                    const float s2 = xx + yy;
+                                    float t = s2 + zz;
+                                    if (euclid && !skip && t < d)
+                                        t = sqrt_class_top(t);
+                                    if (!skip && t < d) {
+                                        d = t;
+                                        changed = true;
+                                    }
+                                    if (tele)
+                                        tl.skipped += skip;
+                                }
+                            }
+                        }
+                        if (changed)
+                            pd[pp] = d;
+                        const unsigned long long um = __ballot(changed);
+                        if (tele && lane == 0) {
+                            tl.updated += (unsigned long long)__popcll(um);
+                            tl.resync += um != 0;
+                        }
+                        if (um)
+                            tile_rekey<4>(lane, lt, ls, cnt, pd, po, trad, tkey, tbest, tthr);
+                        if (clocks && um)
+                            ++tl.arekeys;
+                    }
+                    if (clocks && t_upd)
+                        tl.sub[10] += wall_clock64() - t_upd;
                 }
-                if (clocks && t_upd)
-                    tl.sub[10] += wall_clock64() - t_upd;
-            }
+            };
+            if (P > kWave)
+                pass(std::true_type());
+            else
+                pass(std::false_type());
         }
         if (clocks)
             tl.sub[8] += wall_clock64() - t_mark;
@@ -1230,8 +1235,6 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         if (clocks)
             tl.ph[3] += wall_clock64() - t_mark;
     }
-    if (out_n)
-        write_out(0);  // the last round's selections
     tl.rounds += round;
     __syncthreads();  // LDS is reused by the next cloud
     return true;
@@ -1459,7 +1462,6 @@ RFPS_ROUNDS_KERNEL(k_rfps_rounds_batched_euclid_tele, rounds_batched, true, true
 // RFPS_ERR_TIMEOUT in *status and ends the workgroup.  The launcher clears
 // the slots and out[0..1] first.
 // ---------------------------------------------------------------------------
-constexpr int kProbeMaxWords = 16;
 
 __global__ __launch_bounds__(kBlock) void k_exchange_clear(unsigned long long *board, int words,
                                                            unsigned long long *out)
@@ -1471,6 +1473,9 @@ __global__ __launch_bounds__(kBlock) void k_exchange_clear(unsigned long long *b
         out[t0] = 0ull;
 }
 
+// NW: words per thread (G * W <= kBlock * NW), all of a thread's words in
+// flight at once as in the sampler's exchange
+template <int NW>
 __global__ __launch_bounds__(kBlock) void k_exchange_probe(unsigned long long *board, int G, int W, int rounds,
                                                            unsigned long long *out, uint32_t *status)
 {
@@ -1486,21 +1491,22 @@ __global__ __launch_bounds__(kBlock) void k_exchange_probe(unsigned long long *b
         if (tid < W)
             bstore<Scope::Agent>(sbase + (size_t)rank * kMaxSlotWords + tid,
                                  ((unsigned long long)epoch << 32) | (uint32_t)(rank * W + tid));
-        uint32_t pend = 0;
+        unsigned long long pend = 0;
 #pragma unroll
-        for (int r = 0; r < kProbeMaxWords; ++r)
-            pend |= (tid + kBlock * r < total) ? (1u << r) : 0u;
+        for (int r = 0; r < NW; ++r)
+            pend |= (tid + kBlock * r < total) ? (1ull << r) : 0ull;
         for (uint32_t spin = 0; pend && spin < kSpinLimit; ++spin) {
-            unsigned long long x[kProbeMaxWords];
+            unsigned long long x[NW];
 #pragma unroll
-            for (int r = 0; r < kProbeMaxWords; ++r) {
+            for (int r = 0; r < NW; ++r) {
                 const int e = tid + kBlock * r;
-                x[r] = ((pend >> r) & 1u) ? bload<Scope::Agent>(sbase + (size_t)(e / W) * kMaxSlotWords + e % W) : 0ull;
+                x[r] = ((pend >> r) & 1ull) ? bload<Scope::Agent>(sbase + (size_t)(e / W) * kMaxSlotWords + e % W)
+                                            : 0ull;
             }
 #pragma unroll
-            for (int r = 0; r < kProbeMaxWords; ++r)
-                if (((pend >> r) & 1u) && (uint32_t)(x[r] >> 32) == epoch)
-                    pend &= ~(1u << r);
+            for (int r = 0; r < NW; ++r)
+                if (((pend >> r) & 1ull) && (uint32_t)(x[r] >> 32) == epoch)
+                    pend &= ~(1ull << r);
         }
         if (pend)
             s_abort = 1;
@@ -1518,9 +1524,9 @@ __global__ __launch_bounds__(kBlock) void k_exchange_probe(unsigned long long *b
 hipError_t launch_exchange_probe(unsigned long long *board, int G, int W, int rounds, unsigned long long *out,
                                  uint32_t *status, hipStream_t s)
 {
-    if (G < 1 || G > kMaxGroups || W < 1 || W > kProbeMaxWords || G * W > kBlock * kProbeMaxWords ||
-        2 * G * kMaxSlotWords > kBoardWords || rounds < 1)
+    if (G < 1 || G > kMaxGroups || W < 1 || W > kMaxSlotWords || 2 * G * kMaxSlotWords > kBoardWords || rounds < 1)
         return hipErrorInvalidValue;
+    const int per = (G * W + kBlock - 1) / kBlock;  // words per thread
     k_exchange_clear<<<64, kBlock, 0, s>>>(board, 2 * G * kMaxSlotWords, out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -1528,7 +1534,10 @@ hipError_t launch_exchange_probe(unsigned long long *board, int G, int W, int ro
     void *args[] = {&board, &G, &W, &rounds, &out, &status};
     // unused dynamic LDS of more than half a compute unit's keeps one
     // workgroup per compute unit, as in the sampler
-    const void *fn = reinterpret_cast<const void *>(k_exchange_probe);
+    const void *fn = per <= 2    ? reinterpret_cast<const void *>(k_exchange_probe<2>)
+                     : per <= 16 ? reinterpret_cast<const void *>(k_exchange_probe<16>)
+                     : per <= 32 ? reinterpret_cast<const void *>(k_exchange_probe<32>)
+                                 : reinterpret_cast<const void *>(k_exchange_probe<64>);
     constexpr int kOnePerCu = 96 * 1024;
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kOnePerCu);
     if (e != hipSuccess)
