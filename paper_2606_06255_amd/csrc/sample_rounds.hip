@@ -198,7 +198,7 @@ struct RoundShared {
     uint32_t lkl[kList];                // merge: low halves of their keys (~ original index)
     unsigned long long lset[kList][2];  // merge: listed candidates with larger keys that would lower each one
     uint32_t lrank[kList];              // merge: rank of each listed candidate in key order
-    uint32_t rep;                       // merge: some listed keys are equal (repeats of one point)
+    uint32_t repw[kWavesPerBlock];      // merge: a wavefront's groups repeat a candidate (equal keys)
     uint32_t hist[256];    // merge: candidates per key bucket
     uint32_t my[6 * 8 + 2];  // this workgroup's slot payload (R <= 8)
 };
@@ -567,38 +567,38 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 tl.sub[6] += wall_clock64() - t_mark;
         }
         __syncthreads();
+        // Candidate keys, in registers: thread g (< G <= kBlock) holds group
+        // g's bound and candidate keys; a workgroup without tiles publishes the
+        // bound 0 and no candidates.  The merge's S* (largest bound) and
+        // largest head key are reduced on the way, and repeats of one point
+        // (equal keys, consecutive in a group) are flagged per wavefront.
+        unsigned long long gkey[R];
+        unsigned long long gbound = 0;
         if (!sh.abort) {
-            // candidate keys; a workgroup without tiles publishes the bound 0
-            // and no candidates.  The merge's S* (largest bound) and largest
-            // head key are reduced on the way.
-            unsigned long long sk = 0, hk = 0;
-            for (int g = tid; g < G; g += kBlock) {
-                const unsigned long long bound = bkey[g * (R + 1) + R];
-                const bool empty = bound == 0ull;
+            const int g = tid < G ? tid : 0;
+            gbound = tid < G ? bkey[g * (R + 1) + R] : 0ull;
+            const bool empty = gbound == 0ull;
+            bool repeat = false;
 #pragma unroll
-                for (int s2 = 0; s2 < R; ++s2) {
-                    const int c = g * R + s2;
-                    const unsigned long long k =
-                        empty ? 0ull : ((unsigned long long)__float_as_uint(cld[c]) << 32) | (~corig[c]);
-                    bkey[g * (R + 1) + s2] = k;
-                    if (s2 == 0)
-                        hk = umax64(hk, k);
-                }
-                sk = umax64(sk, bound);
+            for (int s2 = 0; s2 < R; ++s2) {
+                const int c = g * R + s2;
+                gkey[s2] = empty ? 0ull : ((unsigned long long)__float_as_uint(cld[c]) << 32) | (~corig[c]);
+                if (s2 > 0)
+                    repeat = repeat || (gkey[s2] == gkey[s2 - 1] && gkey[s2] != 0ull);
             }
-            sk = wave_max_u64(sk);
-            hk = wave_max_u64(hk);
+            const unsigned long long sk = wave_max_u64(gbound);
+            const unsigned long long hk = wave_max_u64(gkey[0]);
+            const bool anyrep = ballot64(repeat) != 0ull;
             if (lane == 0) {
                 sh.red[wave] = sk;
                 sh.red2[wave] = hk;
+                sh.repw[wave] = anyrep ? 1u : 0u;
             }
             if (tid == 0) {
                 sh.mcount = 0;
                 sh.pfront = 0;
                 sh.pback = 0;
-                sh.rep = 0;
             }
-            sh.hist[tid] = 0;
         }
         __syncthreads();
         if (sh.abort) {
@@ -647,46 +647,55 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             // lookahead returns its lowest index again and again, and its
             // bound equals those candidates.  A group's candidates precede its
             // own bound, so a candidate equal to S* is taken when S* is the
-            // bound of its own group.
-            auto taken = [&](int c, unsigned long long &k) {
-                const int g = c / R;
-                k = c < G * R ? bkey[g * (R + 1) + c % R] : 0ull;
-                return c < G * R && (k > smax || (k == smax && bkey[g * (R + 1) + R] == smax));
-            };
-            // The candidates above S* are compacted (in any order) while a
-            // histogram of their keys' high halves (distance bits, between S*
-            // and the largest key) is counted.
-            const uint32_t hlo = (uint32_t)(smax >> 32);
-            const uint32_t span = (uint32_t)(hmax >> 32) - hlo;
-            const int bits = span ? 32 - __clz((int)span) : 0;
-            const int bshift = bits > 8 ? bits - 8 : 0;
+            // bound of its own group.  The candidates above S* are compacted
+            // (in any order) from the registers, with what the ranking pass
+            // reads staged for the first kList of them.
             const unsigned long long below = lane ? (~0ull >> (kWave - lane)) : 0ull;
-            for (int c0 = 0; c0 < G * R; c0 += kBlock) {
-                const int c = c0 + tid;
-                unsigned long long k;
-                const bool keep = taken(c, k);
-                const unsigned long long km = __ballot(keep);
+            // what the ranking pass reads about listed candidate pos (candidate c, key k)
+            auto stage = [&](uint32_t pos, uint32_t c, unsigned long long k) {
+                sh.lq[pos] = make_float4(cx[c], cy[c], cz[c], __uint_as_float((uint32_t)(k >> 32)));
+                sh.lkl[pos] = (uint32_t)k;
+                sh.lset[pos][1] = 0ull;
+                sh.lrank[pos] = 0u;
+            };
+#pragma unroll
+            for (int s2 = 0; s2 < R; ++s2) {
+                const unsigned long long k = gkey[s2];
+                const bool keep = tid < G && (k > smax || (k == smax && gbound == smax));
+                const unsigned long long km = ballot64(keep);
                 uint32_t base = 0;
                 if (lane == 0 && km)
                     base = atomicAdd(&sh.mcount, (uint32_t)__popcll(km));
                 base = (uint32_t)__shfl((int)base, 0, kWave);
                 if (keep) {
                     const uint32_t pos = base + (uint32_t)__popcll(km & below);
+                    const uint32_t c = (uint32_t)(tid * R + s2);
                     skey[pos] = k;
-                    sidx[pos] = (uint32_t)c;
-                    atomicAdd(&sh.hist[((uint32_t)(k >> 32) - hlo) >> bshift], 1u);
-                    if (c % R != 0 && k == bkey[(c / R) * (R + 1) + c % R - 1])
-                        sh.rep = 1;  // a repeat of the group's previous candidate
+                    sidx[pos] = c;
+                    if (pos < (uint32_t)kList)
+                        stage(pos, c, k);
                 }
             }
             __syncthreads();
             const uint32_t L = sh.mcount;
+            const bool rep = (sh.repw[0] | sh.repw[1] | sh.repw[2] | sh.repw[3]) != 0u;
             uint32_t *ord = reinterpret_cast<uint32_t *>(bkey);  // bkey is not read again this round
             // scur: every listed key is above it (or equals S*, see taken) and
             // every point left out of the list has its true key at most it
             unsigned long long scur = smax;
             uint32_t W = L;  // the list: skey / sidx [0, W)
             if (L > (uint32_t)kList) {
+                // a histogram of the keys' high halves (distance bits, between
+                // S* and the largest key) in 256 buckets
+                const uint32_t hlo = (uint32_t)(smax >> 32);
+                const uint32_t span = (uint32_t)(hmax >> 32) - hlo;
+                const int bits = span ? 32 - __clz((int)span) : 0;
+                const int bshift = bits > 8 ? bits - 8 : 0;
+                sh.hist[tid] = 0;
+                __syncthreads();
+                for (uint32_t i = tid; i < L; i += kBlock)
+                    atomicAdd(&sh.hist[((uint32_t)(skey[i] >> 32) - hlo) >> bshift], 1u);
+                __syncthreads();
                 // msel: the highest bucket whose suffix holds kList candidates
                 if (wave == 0) {
                     uint32_t c4 = 0;
@@ -783,6 +792,10 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     }
                     __syncthreads();
                 }
+                // the list moved: stage it again
+                if ((uint32_t)tid < W)
+                    stage(tid, sidx[tid], skey[tid]);
+                __syncthreads();
             }
             const uint32_t pmax = min(W, (uint32_t)(job.m - j));
             unsigned long long t_sub = 0;
@@ -793,22 +806,18 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 tl.listed += W;
             }
 
-            // Ranks and lowering sets.  Lanes take listed candidates q (two
-            // chunks of 64), wavefronts take candidates i (two at a time).
-            // For each i, ballots give the set of q with a larger key that
-            // would lower i (state value of their distance below i's listed
-            // distance) and i's rank in key order (larger keys, then equal
-            // keys listed before it: only repeats of one point are equal).
-            // Every ballot is of a single comparison, so its lane mask is
-            // used as it is.
-            if ((uint32_t)tid < W) {
-                const uint32_t c = sidx[tid];
-                const unsigned long long k = skey[tid];
-                sh.lq[tid] = make_float4(cx[c], cy[c], cz[c], __uint_as_float((uint32_t)(k >> 32)));
-                sh.lkl[tid] = (uint32_t)k;
-            }
-            __syncthreads();
-            const bool two = W > (uint32_t)kWave;  // a second chunk of candidates
+            // Ranks and lowering sets: for every listed candidate i, the set of
+            // listed candidates q with a larger key that would lower it (state
+            // value of their distance below i's listed distance), as two
+            // 64-bit words (q < 64, q >= 64), and its rank in key order
+            // (larger keys, then equal keys listed before it: only repeats of
+            // one point are equal).  For q < 64, lanes take q and
+            // wavefronts take i, two at a time, and one ballot gives a word;
+            // the few q >= 64 are taken the other way round (lanes take i,
+            // wavefronts share the q) so that no pass runs over a nearly empty
+            // chunk of lanes.  Every ballot is of a single comparison, so its
+            // lane mask is used as it is.
+            const bool two = W > (uint32_t)kWave;  // some candidates are q >= 64
             const unsigned long long v0 = ballot64((uint32_t)lane < W);
             const unsigned long long v1 = ballot64((uint32_t)lane + kWave < W);
             const float4 q0 = sh.lq[lane];
@@ -817,79 +826,81 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             const unsigned long long k1 =
                 ((unsigned long long)__float_as_uint(q1.w) << 32) | sh.lkl[two ? lane + kWave : lane];
             {
-                uint32_t r0l = 0, r0h = 0, r1l = 0, r1h = 0, rrk = 0;
-                // both candidates of a pass and both chunks are straight-line
-                // code (the second chunk is a compile-time case), so their
-                // independent chains interleave
-                auto pass = [&](auto two_c) {
-                    constexpr bool TWO = decltype(two_c)::value;
-                    int t = 0;
-                    for (uint32_t i = (uint32_t)wave; i < W; i += 2 * kWavesPerBlock, t += 2) {
-                        // the second candidate may lie past the list: its
-                        // results are not kept
-                        const uint32_t i2 = i + kWavesPerBlock < W ? i + kWavesPerBlock : i;
-                        const float4 qa = sh.lq[i], qb = sh.lq[i2];
-                        const unsigned long long ka = ((unsigned long long)__float_as_uint(qa.w) << 32) | sh.lkl[i];
-                        const unsigned long long kb = ((unsigned long long)__float_as_uint(qb.w) << 32) | sh.lkl[i2];
-                        const float da0 = sqdist(qa.x, qa.y, qa.z, q0.x, q0.y, q0.z);
-                        const float db0 = sqdist(qb.x, qb.y, qb.z, q0.x, q0.y, q0.z);
-                        const unsigned long long ga0 = ballot64(k0 > ka) & v0, gb0 = ballot64(k0 > kb) & v0;
-                        bool ba0 = da0 < qa.w, bb0 = db0 < qb.w;
-                        if (euclid) {
-                            ba0 = ba0 && sqrt_class_top(da0) < qa.w;
-                            bb0 = bb0 && sqrt_class_top(db0) < qb.w;
-                        }
-                        const unsigned long long ma0 = ballot64(ba0) & ga0, mb0 = ballot64(bb0) & gb0;
-                        uint32_t rka = (uint32_t)__popcll(ga0), rkb = (uint32_t)__popcll(gb0);
-                        unsigned long long ma1 = 0, mb1 = 0;
-                        if constexpr (TWO) {
-                            const float da1 = sqdist(qa.x, qa.y, qa.z, q1.x, q1.y, q1.z);
-                            const float db1 = sqdist(qb.x, qb.y, qb.z, q1.x, q1.y, q1.z);
-                            const unsigned long long ga1 = ballot64(k1 > ka) & v1, gb1 = ballot64(k1 > kb) & v1;
-                            bool ba1 = da1 < qa.w, bb1 = db1 < qb.w;
-                            if (euclid) {
-                                ba1 = ba1 && sqrt_class_top(da1) < qa.w;
-                                bb1 = bb1 && sqrt_class_top(db1) < qb.w;
-                            }
-                            ma1 = ballot64(ba1) & ga1;
-                            mb1 = ballot64(bb1) & gb1;
-                            rka += (uint32_t)__popcll(ga1);
-                            rkb += (uint32_t)__popcll(gb1);
-                        }
-                        // lane t keeps the results of this wavefront's t-th candidate
-                        const bool sa = lane == t, sb = lane == t + 1;
-                        r0l = sa ? (uint32_t)ma0 : sb ? (uint32_t)mb0 : r0l;
-                        r0h = sa ? (uint32_t)(ma0 >> 32) : sb ? (uint32_t)(mb0 >> 32) : r0h;
-                        r1l = sa ? (uint32_t)ma1 : sb ? (uint32_t)mb1 : r1l;
-                        r1h = sa ? (uint32_t)(ma1 >> 32) : sb ? (uint32_t)(mb1 >> 32) : r1h;
-                        rrk = sa ? rka : sb ? rkb : rrk;
+                uint32_t r0l = 0, r0h = 0, rrk = 0;
+                int t = 0;
+                for (uint32_t i = (uint32_t)wave; i < W; i += 2 * kWavesPerBlock, t += 2) {
+                    // two independent candidates per pass (the second may lie
+                    // past the list: its results are not kept)
+                    const uint32_t i2 = i + kWavesPerBlock < W ? i + kWavesPerBlock : i;
+                    const float4 qa = sh.lq[i], qb = sh.lq[i2];
+                    const unsigned long long ka = ((unsigned long long)__float_as_uint(qa.w) << 32) | sh.lkl[i];
+                    const unsigned long long kb = ((unsigned long long)__float_as_uint(qb.w) << 32) | sh.lkl[i2];
+                    const float da = sqdist(qa.x, qa.y, qa.z, q0.x, q0.y, q0.z);
+                    const float db = sqdist(qb.x, qb.y, qb.z, q0.x, q0.y, q0.z);
+                    const unsigned long long ga = ballot64(k0 > ka) & v0, gb = ballot64(k0 > kb) & v0;
+                    bool ba = da < qa.w, bb = db < qb.w;
+                    if (euclid) {
+                        ba = ba && sqrt_class_top(da) < qa.w;
+                        bb = bb && sqrt_class_top(db) < qb.w;
                     }
-                };
-                if (two)
-                    pass(std::true_type());
-                else
-                    pass(std::false_type());
-                if (sh.rep) {
-                    // equal keys (repeats of one point): those listed before a
-                    // candidate also rank above it
-                    int t = 0;
-                    for (uint32_t i = (uint32_t)wave; i < W; i += kWavesPerBlock, ++t) {
-                        const float4 qi = sh.lq[i];
-                        const unsigned long long ki = ((unsigned long long)__float_as_uint(qi.w) << 32) | sh.lkl[i];
-                        const uint32_t il = i & (kWave - 1);
-                        const unsigned long long before = il ? ~0ull >> (kWave - il) : 0ull;
-                        const unsigned long long e0 = ballot64(k0 == ki) & v0 & (i >= (uint32_t)kWave ? ~0ull : before);
-                        const unsigned long long e1 = ballot64(k1 == ki) & v1 & (i >= (uint32_t)kWave ? before : 0ull);
-                        if (lane == t)
-                            rrk += (uint32_t)(__popcll(e0) + __popcll(e1));
-                    }
+                    const unsigned long long ma = ballot64(ba) & ga, mb = ballot64(bb) & gb;
+                    // lane t keeps the results of this wavefront's t-th candidate
+                    const bool sa = lane == t, sb = lane == t + 1;
+                    r0l = sa ? (uint32_t)ma : sb ? (uint32_t)mb : r0l;
+                    r0h = sa ? (uint32_t)(ma >> 32) : sb ? (uint32_t)(mb >> 32) : r0h;
+                    rrk = sa ? (uint32_t)__popcll(ga) : sb ? (uint32_t)__popcll(gb) : rrk;
                 }
-                // lane t holds the results of this wavefront's t-th candidate
                 const uint32_t i = (uint32_t)wave + (uint32_t)kWavesPerBlock * (uint32_t)lane;
                 if (i < W) {
                     sh.lset[i][0] = ((unsigned long long)r0h << 32) | r0l;
-                    sh.lset[i][1] = ((unsigned long long)r1h << 32) | r1l;
-                    sh.lrank[i] = rrk;
+                    atomicAdd(&sh.lrank[i], rrk);
+                }
+            }
+            if (two) {
+                // q >= 64: lane l takes candidates l and l + 64, wavefront w
+                // the q = 64 + w, 64 + w + 4, ...
+                unsigned long long s0 = 0, s1 = 0;
+                uint32_t c0 = 0, c1 = 0;
+                for (uint32_t q = (uint32_t)kWave + wave; q < W; q += kWavesPerBlock) {
+                    const float4 qq = sh.lq[q];
+                    const unsigned long long kq = ((unsigned long long)__float_as_uint(qq.w) << 32) | sh.lkl[q];
+                    const unsigned long long bit = 1ull << (q - kWave);
+                    const float d0 = sqdist(q0.x, q0.y, q0.z, qq.x, qq.y, qq.z);
+                    const float d1 = sqdist(q1.x, q1.y, q1.z, qq.x, qq.y, qq.z);
+                    bool b0 = d0 < q0.w, b1 = d1 < q1.w;
+                    if (euclid) {
+                        b0 = b0 && sqrt_class_top(d0) < q0.w;
+                        b1 = b1 && sqrt_class_top(d1) < q1.w;
+                    }
+                    const bool g0 = kq > k0, g1 = kq > k1;
+                    s0 |= (b0 && g0) ? bit : 0ull;
+                    s1 |= (b1 && g1) ? bit : 0ull;
+                    c0 += g0 ? 1u : 0u;
+                    c1 += g1 ? 1u : 0u;
+                }
+                if ((uint32_t)lane < W) {
+                    if (s0)
+                        atomicOr(&sh.lset[lane][1], s0);
+                    atomicAdd(&sh.lrank[lane], c0);
+                }
+                if ((uint32_t)lane + kWave < W) {
+                    if (s1)
+                        atomicOr(&sh.lset[lane + kWave][1], s1);
+                    atomicAdd(&sh.lrank[lane + kWave], c1);
+                }
+            }
+            if (rep) {
+                // equal keys (repeats of one point): those listed before a
+                // candidate also rank above it
+                for (uint32_t i = (uint32_t)wave; i < W; i += kWavesPerBlock) {
+                    const float4 qi = sh.lq[i];
+                    const unsigned long long ki = ((unsigned long long)__float_as_uint(qi.w) << 32) | sh.lkl[i];
+                    const uint32_t il = i & (kWave - 1);
+                    const unsigned long long before = il ? ~0ull >> (kWave - il) : 0ull;
+                    const unsigned long long e0 = ballot64(k0 == ki) & v0 & (i >= (uint32_t)kWave ? ~0ull : before);
+                    const unsigned long long e1 = ballot64(k1 == ki) & v1 & (i >= (uint32_t)kWave ? before : 0ull);
+                    if (lane == 0 && (e0 | e1))
+                        atomicAdd(&sh.lrank[i], (uint32_t)(__popcll(e0) + __popcll(e1)));
                 }
             }
             __syncthreads();
