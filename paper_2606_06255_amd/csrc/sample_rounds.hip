@@ -139,17 +139,16 @@ __global__ __launch_bounds__(kBlock) void k_rounds_plan(IndexHeader *hdr, const 
         set_status(&hdr->sample_status, RFPS_ERR_CAPACITY);
 }
 
-// One wavefront recomputes the key, best point and threshold of tile lt from
-// the distances in D (all lanes of the wave must call it).  The threshold
-// goes to tthr[lt * TS].
+// One wavefront recomputes the key, best point and threshold of tile lt
+// (points ls .. ls + cnt - 1) from each lane's distance d and original index
+// o of its point, held in registers (all lanes of the wave must call it).
+// The threshold goes to tthr[lt * TS].
 template <int TS>
-__device__ __forceinline__ void tile_rekey(int lane, uint32_t lt, uint32_t ls, uint32_t cnt, const float *D,
-                                           const uint32_t *po, const float *trad, unsigned long long *tkey,
-                                           uint32_t *tbest, float *tthr)
+__device__ __forceinline__ void tile_rekey(int lane, uint32_t lt, uint32_t ls, uint32_t cnt, float d, uint32_t o,
+                                           const float *trad, unsigned long long *tkey, uint32_t *tbest, float *tthr)
 {
     const bool valid = (uint32_t)lane < cnt;
-    const uint32_t p = ls + (valid ? lane : 0);
-    const unsigned long long key = valid ? pack_key(D[p], po[p]) : 0ull;
+    const unsigned long long key = valid ? pack_key(d, o) : 0ull;
     const unsigned long long kmax = wave_max_u64(key);
     const unsigned long long hit = ballot64(key == kmax) & ballot64(valid);
     if (lane == 0) {
@@ -339,6 +338,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             const uint32_t meta = tmeta[lt];
             const uint32_t ls = meta & 0xffffu, c = meta >> 16;
             const uint32_t gs = a.tstart[job.tb + rank + (size_t)lt * G];
+            float dp = 0.0f;
+            uint32_t op = 0;
             if ((uint32_t)lane < c) {
                 const uint32_t i = gs + lane, p = ls + lane;
                 const float x = a.xs[i], y = a.ys[i], z = a.zs[i];
@@ -346,10 +347,12 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 py[p] = y;
                 pz[p] = z;
                 const float d0 = sqdist(x, y, z, sx, sy, sz);
-                pd[p] = euclid ? sqrt_class_top(d0) : d0;
-                po[p] = a.orig[i] - job.point_base;
+                dp = euclid ? sqrt_class_top(d0) : d0;
+                op = a.orig[i] - job.point_base;
+                pd[p] = dp;
+                po[p] = op;
             }
-            tile_rekey<4>(lane, lt, ls, c, pd, po, trad, tkey, tbest, tthr);
+            tile_rekey<4>(lane, lt, ls, c, dp, op, trad, tkey, tbest, tthr);
         }
         if (tid == 0) {
             sh.list_n = 0;
@@ -455,11 +458,10 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                         const uint32_t ls = meta & 0xffffu, cnt = meta >> 16;
                         const bool valid = (uint32_t)lane < cnt;
                         const uint32_t pp = ls + (valid ? lane : 0);
-                        if (!tflag[t]) {
-                            if (valid)
-                                pdl[pp] = pd[pp];
-                        }
-                        float d = pdl[pp];
+                        // the private copy starts from the true state the
+                        // first time a step of this round touches the tile
+                        const float dpl = pdl[pp], dpt = pd[pp];
+                        float d = tflag[t] ? dpl : dpt;
                         bool upd = false;
                         if (valid) {
                             const float dx = px[pp] - lx, dy = py[pp] - ly, dz = pz[pp] - lz;
@@ -470,15 +472,13 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                             if (euclid && !skip && tt < d)
                                 tt = sqrt_class_top(tt);
                             upd = !skip && tt < d;
-                            if (upd) {
-                                d = tt;
-                                pdl[pp] = tt;
-                            }
+                            d = upd ? tt : d;
+                            pdl[pp] = d;
                         }
                         if (lane == 0)
                             tflag[t] = 1;
                         if (__ballot(upd))
-                            tile_rekey<1>(lane, t, ls, cnt, pdl, po, trad, tkeyl, tbestl, tthrl);
+                            tile_rekey<1>(lane, t, ls, cnt, d, po[pp], trad, tkeyl, tbestl, tthrl);
                     }
                 }
             }
@@ -1225,7 +1225,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                             tl.resync += um != 0;
                         }
                         if (um)
-                            tile_rekey<4>(lane, lt, ls, cnt, pd, po, trad, tkey, tbest, tthr);
+                            tile_rekey<4>(lane, lt, ls, cnt, d, po[pp], trad, tkey, tbest, tthr);
                         if (clocks && um)
                             ++tl.arekeys;
                     }
