@@ -19,10 +19,18 @@ generates clouds (half room-like, half LiDAR-like, N log-uniform in
 every cloud (the sweep), trains the network on the training clouds and
 evaluates its choices on held-out clouds and on the dense 1M-point LiDAR-like
 cloud against the default rule and the best candidate of the sweep.
+
+A sweep too long for one session is measured in slices and merged:
+    python -m paper_2606_06255_amd.param_model --out DIR --part START COUNT
+    python -m paper_2606_06255_amd.param_model --out DIR --merge PART.npz ...
+    python -m paper_2606_06255_amd.param_model --out DIR --sweep DIR/sweep.npz
+(cloud index total = train + held-out is the dense 1M-point cloud; every
+slice regenerates its clouds from the seed, so slices are independent).
 """
 from __future__ import annotations
 
 import argparse
+import concurrent.futures as cf
 import json
 import math
 import os
@@ -119,9 +127,10 @@ def make_cloud(seed: int, i: int, n: int) -> np.ndarray:
     return synth.lidar(ss, beams=beams, azimuth_steps=steps, n_out=n)
 
 
-def sweep_cloud(x: torch.Tensor, m: int, idx=None):
-    """Build + sample time (ms) and pruning rate of every candidate on one
-    cloud, one timed run each after one warm-up run of the default."""
+def sweep_cloud(x: torch.Tensor, m: int, idx=None, repeats: int = 1, prune_rates: bool = True):
+    """Build + sample time (ms, the median of `repeats` timed runs) and
+    pruning rate (NaN unless prune_rates) of every candidate on one cloud,
+    after one warm-up run of the default."""
     stream = torch.cuda.current_stream(x.device)
     n = x.shape[0]
     out_i = torch.empty(m, dtype=torch.int32, device=x.device)
@@ -136,18 +145,24 @@ def sweep_cloud(x: torch.Tensor, m: int, idx=None):
     for k, (nv, sh) in enumerate(candidates()):
         # the time is the default (uninstrumented) sampler's; a second,
         # untimed call with telemetry gives the pruning rate
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        idx = build_index(x, n_vox=nv, shell=sh, reuse=idx)
-        sample(idx, m, 0, out_idx=out_i, out_d2=out_d)
-        b.record(stream)
-        torch.cuda.synchronize()
+        times = []
+        for _ in range(repeats):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            idx = build_index(x, n_vox=nv, shell=sh, reuse=idx)
+            sample(idx, m, 0, out_idx=out_i, out_d2=out_d)
+            b.record(stream)
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+            if read_status(idx) != 0:
+                break
         st = read_status(idx)
         if st == 0:
             if not torch.equal(out_i, ref):
                 raise RuntimeError("candidate %d changed the sampled sequence" % k)
-            sample(idx, m, 0, flags=F_TELEMETRY, out_idx=out_i, out_d2=out_d)
-            st = read_status(idx)
+            if prune_rates:
+                sample(idx, m, 0, flags=F_TELEMETRY, out_idx=out_i, out_d2=out_d)
+                st = read_status(idx)
         if st == 6:
             # this grid's share per workgroup does not fit on chip: not a choice
             ms[k], prune[k] = np.nan, np.nan
@@ -156,9 +171,12 @@ def sweep_cloud(x: torch.Tensor, m: int, idx=None):
             raise RuntimeError("candidate %d failed with status %d" % (k, st))
         if not torch.equal(out_i, ref):
             raise RuntimeError("candidate %d changed the sampled sequence" % k)
-        tel = read_telemetry(idx)
-        ms[k] = a.elapsed_time(b)
-        prune[k] = 1.0 - tel["points_visited"] / max(1, tel["iters"] * n)
+        ms[k] = float(np.median(times))
+        if prune_rates:
+            tel = read_telemetry(idx)
+            prune[k] = 1.0 - tel["points_visited"] / max(1, tel["iters"] * n)
+        else:
+            prune[k] = np.nan
     return ms, prune, idx
 
 
@@ -169,19 +187,22 @@ def targets(ms, prune):
     ok = np.isfinite(ms)
     lm = np.log(np.where(ok, ms, 1.0))
     lm[~ok] = lm[ok].max() + math.log(2.0)
-    pr = np.where(ok, prune, 0.0)
+    pr = np.where(np.isfinite(prune), prune, 0.0)
     return np.concatenate([lm - lm.mean(), pr]).astype(np.float32)
 
 
-def train(X, T, device, steps=4000, lr=1e-3, seed=0, log=None):
+def train(X, T, device, steps=4000, lr=1e-3, seed=0, log=None, has_prune=None):
     """Full-batch Adam on the GPU with the library's training kernels."""
     net = MLP(device, rows=X.shape[0])
     net.load(init_params(seed))
     Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(device)
     Td = torch.from_numpy(np.ascontiguousarray(T, dtype=np.float32)).to(device)
-    # the ranking head counts fully, the pruning-rate head a quarter
+    # the ranking head counts fully, the pruning-rate head a quarter (and not
+    # at all for clouds swept without pruning rates)
     W = np.ones_like(T)
     W[:, MLP_CANDIDATES:] = 0.25
+    if has_prune is not None:
+        W[~np.asarray(has_prune), MLP_CANDIDATES:] = 0.0
     Wd = torch.from_numpy(W).to(device)
     loss = torch.empty(1, dtype=torch.float32, device=device)
     hist = []
@@ -214,82 +235,126 @@ def evaluate(net, X, MS, N, margin):
     return {"gain_vs_default": gain, "regret_vs_best": regret, "best_vs_default": headroom, "clouds": rows}
 
 
+def cloud_sizes(seed: int, total: int, n_min: int, n_max: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return np.floor(np.exp(rng.uniform(math.log(n_min), math.log(n_max), total))).astype(np.int64)
+
+
+def sweep_range(args, start: int, count: int, dev, log, save=None):
+    """Sweeps clouds [start, start + count) of the set (index total = the
+    dense 1M-point cloud); cloud generation runs ahead on host threads.
+    save(X, MS, PR, N, I) is called every 25 clouds with what is done."""
+    import synth
+    total = args.train_clouds + args.heldout_clouds
+    sizes = cloud_sizes(args.seed, total, args.n_min, args.n_max)
+    ids = list(range(start, min(start + count, total + 1)))
+
+    def gen(i):
+        if i < total:
+            n = int(sizes[i])
+            return make_cloud(args.seed, i, n), n // 4
+        P = synth.dense_lidar(0)
+        return P, 65536
+
+    net = MLP(dev)
+    X = np.zeros((len(ids), MLP_INPUTS), dtype=np.float32)
+    MS = np.zeros((len(ids), MLP_CANDIDATES))
+    PR = np.zeros((len(ids), MLP_CANDIDATES))
+    N = np.zeros(len(ids), dtype=np.int64)
+    idx = None
+    t0 = time.time()
+    with cf.ThreadPoolExecutor(max_workers=4) as ex:
+        futs = [ex.submit(gen, i) for i in ids[:4]]
+        for r, i in enumerate(ids):
+            P, m = futs[r].result()
+            if r + 4 < len(ids):
+                futs.append(ex.submit(gen, ids[r + 4]))
+            n = P.shape[0]
+            x = torch.from_numpy(P).to(dev)
+            X[r] = net.features(x).cpu().numpy()
+            # pruning rates are a secondary training target: every
+            # args.prune_every-th training cloud (and the dense cloud)
+            MS[r], PR[r], idx = sweep_cloud(x, m, idx, repeats=args.repeats,
+                                            prune_rates=(i < args.train_clouds and i % args.prune_every == 0)
+                                            or i == total)
+            N[r] = n
+            log("cloud %d (%d/%d) N=%d M=%d default %.2f ms best %.2f ms (cand %d) worst %.2f ms, %d unfit  [%.0f s]" % (
+                i, r + 1, len(ids), n, m, MS[r, default_candidate(n)], np.nanmin(MS[r]), int(np.nanargmin(MS[r])),
+                np.nanmax(MS[r]), int(np.isnan(MS[r]).sum()), time.time() - t0))
+            if save is not None and (r % 25 == 24 or r == len(ids) - 1):
+                save(X[:r + 1], MS[:r + 1], PR[:r + 1], N[:r + 1], np.array(ids[:r + 1], dtype=np.int64))
+    return X, MS, PR, N, np.array(ids, dtype=np.int64)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="sweep, train and evaluate the voxel-parameter network")
     ap.add_argument("--out", required=True)
-    ap.add_argument("--train-clouds", type=int, default=256)
-    ap.add_argument("--heldout-clouds", type=int, default=32)
+    ap.add_argument("--train-clouds", type=int, default=2000)
+    ap.add_argument("--heldout-clouds", type=int, default=200)
     ap.add_argument("--n-min", type=int, default=8000)
     ap.add_argument("--n-max", type=int, default=1 << 20)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--repeats", type=int, default=3, help="timed runs per candidate (median)")
+    ap.add_argument("--prune-every", type=int, default=4,
+                    help="measure pruning rates on every n-th training cloud (a second, instrumented run)")
+    ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--margin", type=float, default=0.03)
     ap.add_argument("--seed", type=int, default=2606)
-    ap.add_argument("--sweep", default="", help="reuse a saved sweep (npz) instead of measuring")
+    ap.add_argument("--sweep", default="", help="train on a saved sweep (npz) instead of measuring")
+    ap.add_argument("--part", type=int, nargs=2, metavar=("START", "COUNT"),
+                    help="only sweep clouds [START, START + COUNT) and save them as a part")
+    ap.add_argument("--merge", nargs="+", default=None, help="merge saved parts into OUT/sweep.npz and stop")
     args = ap.parse_args(argv)
     os.makedirs(args.out, exist_ok=True)
 
     def log(*a):
         print(*a, flush=True)
 
+    total = args.train_clouds + args.heldout_clouds
+    if args.merge:
+        parts = [np.load(f, allow_pickle=False) for f in args.merge]
+        I = np.concatenate([d["I"] for d in parts])
+        order = np.argsort(I)
+        if not np.array_equal(I[order], np.arange(total + 1)):
+            raise SystemExit("parts do not cover clouds 0..%d exactly once" % total)
+        out = {k: np.concatenate([d[k] for d in parts])[order] for k in ("X", "MS", "PR", "N")}
+        np.savez(os.path.join(args.out, "sweep.npz"), I=I[order], **out)
+        log("merged %d clouds into %s" % (I.size, os.path.join(args.out, "sweep.npz")))
+        return 0
+
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    total = args.train_clouds + args.heldout_clouds
+    if args.part:
+        start, count = args.part
+        path = os.path.join(args.out, "sweep_part_%05d.npz" % start)
+
+        def save(X, MS, PR, N, I):
+            np.savez(path + ".tmp.npz", X=X, MS=MS, PR=PR, N=N, I=I)
+            os.replace(path + ".tmp.npz", path)
+
+        sweep_range(args, start, count, dev, log, save=save)
+        log("saved %s" % path)
+        return 0
     if args.sweep:
-        # reuse measured times; the features are recomputed on the GPU from
-        # the regenerated clouds (same seeds and sizes)
         d = np.load(args.sweep, allow_pickle=False)
-        MS, PR, N = d["MS"], d["PR"], d["N"]
-        X = np.zeros((N.size, MLP_INPUTS), dtype=np.float32)
-        net = MLP(dev)
-        for i in range(N.size):
-            if i < N.size - 1:
-                P = make_cloud(args.seed, i, int(N[i]))
-            else:
-                import synth
-                P = synth.dense_lidar(0)
-            X[i] = net.features(torch.from_numpy(P).to(dev)).cpu().numpy()
-            if i % 32 == 31:
-                log("features %d/%d" % (i + 1, N.size))
-        np.savez(os.path.join(args.out, "sweep.npz"), X=X, MS=MS, PR=PR, N=N)
+        X, MS, PR, N = d["X"], d["MS"], d["PR"], d["N"]
+        if X.shape[0] != total + 1:
+            raise SystemExit("the sweep holds %d clouds, expected %d" % (X.shape[0], total + 1))
     else:
-        rng = np.random.default_rng(args.seed)
-        sizes = np.floor(np.exp(rng.uniform(math.log(args.n_min), math.log(args.n_max), total))).astype(np.int64)
-        net = MLP(dev)
-        X = np.zeros((total + 1, MLP_INPUTS), dtype=np.float32)
-        MS = np.zeros((total + 1, MLP_CANDIDATES))
-        PR = np.zeros((total + 1, MLP_CANDIDATES))
-        N = np.zeros(total + 1, dtype=np.int64)
-        idx = None
-        t0 = time.time()
-        for i in range(total + 1):
-            if i < total:
-                P, n = make_cloud(args.seed, i, int(sizes[i])), int(sizes[i])
-                m = n // 4
-            else:
-                import synth
-                P = synth.dense_lidar(0)
-                n, m = P.shape[0], 65536
-            x = torch.from_numpy(P).to(dev)
-            X[i] = net.features(x).cpu().numpy()
-            MS[i], PR[i], idx = sweep_cloud(x, m, idx)
-            N[i] = n
-            log("cloud %d/%d N=%d M=%d default %.2f ms best %.2f ms (cand %d) worst %.2f ms, %d unfit  [%.0f s]" % (
-                i + 1, total + 1, n, m, MS[i, default_candidate(n)], np.nanmin(MS[i]), int(np.nanargmin(MS[i])),
-                np.nanmax(MS[i]), int(np.isnan(MS[i]).sum()), time.time() - t0))
-            if i % 16 == 15 or i == total:
-                np.savez(os.path.join(args.out, "sweep.npz"), X=X[:i + 1], MS=MS[:i + 1], PR=PR[:i + 1],
-                         N=N[:i + 1])
+        X, MS, PR, N, _ = sweep_range(args, 0, total + 1, dev, log)
+        np.savez(os.path.join(args.out, "sweep.npz"), X=X, MS=MS, PR=PR, N=N, I=np.arange(total + 1))
     ntr = args.train_clouds
     T = np.stack([targets(MS[i], PR[i]) for i in range(X.shape[0])])
+    has_prune = np.isfinite(PR).any(axis=1)
     log("training on %d clouds" % ntr)
-    net, hist = train(X[:ntr], T[:ntr], dev, steps=args.steps, lr=args.lr, seed=args.seed, log=log)
+    net, hist = train(X[:ntr], T[:ntr], dev, steps=args.steps, lr=args.lr, seed=args.seed, log=log,
+                      has_prune=has_prune[:ntr])
     params = net.save()
     report = {"train": evaluate(net, X[:ntr], MS[:ntr], N[:ntr], args.margin),
               "heldout": evaluate(net, X[ntr:-1], MS[ntr:-1], N[ntr:-1], args.margin),
               "dense_lidar_1M": evaluate(net, X[-1:], MS[-1:], N[-1:], args.margin),
               "loss": hist, "margin": args.margin, "train_clouds": ntr, "heldout_clouds": int(X.shape[0] - ntr - 1),
-              "steps": args.steps, "lr": args.lr, "seed": args.seed}
+              "steps": args.steps, "lr": args.lr, "seed": args.seed, "repeats": args.repeats}
     for k in ("train", "heldout", "dense_lidar_1M"):
         r = report[k]
         log("%s: gain vs default %.3fx, regret vs best %.3fx, best vs default %.3fx" % (
