@@ -78,6 +78,11 @@ struct RoundArgs {
 // (the merge stops there; a shorter round is always valid).
 constexpr int kList = 2 * kWave;
 constexpr int kMaxRoundPicks = kList;
+// Tiles a wavefront tests per pass of the apply phase (their sphere loads are
+// in flight together; 8 measured faster than 4 or 16).
+constexpr int kApplyTiles = 8;
+// Listed candidates a wavefront ranks per pass of the merge's ranking loop.
+constexpr int kRankPerPass = 2;
 
 
 // Value of lane l of v (l uniform).
@@ -111,10 +116,19 @@ __host__ __device__ __forceinline__ uint32_t merge_words(uint32_t G, uint32_t R)
     return keys > picks ? keys : picks;
 }
 
+// Tile spheres a workgroup keeps: its tile count rounded up to whole passes
+// of the apply phase (kApplyTiles per wavefront), at least one pass; the
+// padding never passes a test.
+__host__ __device__ __forceinline__ uint32_t padded_tiles(uint32_t tiles)
+{
+    constexpr uint32_t q = (uint32_t)(kApplyTiles * kWavesPerBlock);
+    return tiles ? (tiles + q - 1) / q * q : q;
+}
+
 __host__ __device__ __forceinline__ uint32_t rounds_lds_need(uint32_t tiles, uint32_t pts, uint32_t G, uint32_t R)
 {
-    return tiles * 60u + pts * 24u + G * R * 24u + G * (R + 1u) * 8u + sort_cap(G, R) * 4u + merge_words(G, R) * 4u +
-           128u;
+    return tiles * 40u + padded_tiles(tiles) * 16u + pts * 24u + G * R * 24u + G * (R + 1u) * 8u +
+           sort_cap(G, R) * 4u + merge_words(G, R) * 4u + 128u;
 }
 
 // Capacity plan of one team of G workgroups over the tiles [tb, te).
@@ -266,14 +280,14 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         ~(size_t)15;
     float4 *tsph = reinterpret_cast<float4 *>(smem + tsph_off);
     float *tthr = reinterpret_cast<float *>(tsph) + 3;  // with stride 4
-    float *trad = reinterpret_cast<float *>(tsph + ntl);
+    const int ntlp = (int)padded_tiles((uint32_t)ntl);
+    float *trad = reinterpret_cast<float *>(tsph + ntlp);
     float *tthrl = trad + ntl;
     uint32_t *tmeta = reinterpret_cast<uint32_t *>(tthrl + ntl);
     uint32_t *tbest = tmeta + ntl;
     uint32_t *tbestl = tbest + ntl;
     uint32_t *tflag = tbestl + ntl;
-    uint32_t *tlist = tflag + ntl;
-    float *cx = reinterpret_cast<float *>(tlist + ntl);  // [G][R] candidates
+    float *cx = reinterpret_cast<float *>(tflag + ntl);  // [G][R] candidates
     float *cy = cx + G * R;
     float *cz = cy + G * R;
     float *cld = cz + G * R;  // local d2 (the selection d2 of a certified candidate)
@@ -311,6 +325,9 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         trad[lt] = a.trad[t];
         off += c;
     }
+    // padding spheres: no squared distance is below a threshold of -inf
+    for (int lt = ntl + tid; lt < ntlp; lt += kBlock)
+        tsph[lt] = make_float4(0.0f, 0.0f, 0.0f, -INFINITY);
     float *py = px + npl;
     float *pz = py + npl;
     float *pd = pz + npl;
@@ -375,11 +392,29 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         // need no workgroup barrier.  Lanes take tiles for the arg max and the
         // sphere tests; a tile that the test keeps is updated by all lanes.
         if (wave == 0) {
-            for (int lt = lane; lt < ntl; lt += kWave) {
-                tkeyl[lt] = tkey[lt];
-                tthrl[lt] = tsph[lt].w;
-                tbestl[lt] = tbest[lt];
-                tflag[lt] = 0;
+            // The private tile state starts from the true one; the first
+            // step's arg max over the tile keys is taken on the way.
+            unsigned long long lk = 0, lk2 = 0;  // the lane's two largest tile keys
+            uint32_t lt_best = 0;
+            // same trip count on every lane, loads clamped: no branches
+            for (int lt0 = 0; lt0 < ntl; lt0 += kWave) {
+                const int lt = lt0 + lane;
+                const bool tin = lt < ntl;
+                const int li = tin ? lt : 0;
+                const unsigned long long kr = tkey[li];
+                const float th = tsph[li].w;
+                const uint32_t tb = tbest[li];
+                if (tin) {
+                    tkeyl[lt] = kr;
+                    tthrl[lt] = th;
+                    tbestl[lt] = tb;
+                    tflag[lt] = 0;
+                }
+                const unsigned long long k = tin ? kr : 0ull;
+                const bool top = k > lk;
+                lk2 = top ? lk : umax64(lk2, k);
+                lt_best = top ? (uint32_t)lt : lt_best;
+                lk = top ? k : lk;
             }
             if (clocks) {
                 const unsigned long long t = wall_clock64();
@@ -387,20 +422,23 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 tl.sub[5] -= t;  // the steps end at the phase mark below
             }
             for (int s = 0; s <= R; ++s) {
-                // arg max over the local tile keys (key and tile travel together)
+                // arg max over the local tile keys (key and tile travel
+                // together; step 0's was taken with the copy)
                 if (clocks)
                     tl.sub[9] -= wall_clock64();
-                unsigned long long lk = 0, lk2 = 0;  // the lane's two largest tile keys
-                uint32_t lt_best = 0;
-                // same trip count on every lane, loads clamped: no branches
-                for (int lt0 = 0; lt0 < ntl; lt0 += kWave) {
-                    const int lt = lt0 + lane;
-                    const unsigned long long kr = tkeyl[lt < ntl ? lt : 0];
-                    const unsigned long long k = lt < ntl ? kr : 0ull;
-                    const bool top = k > lk;
-                    lk2 = top ? lk : umax64(lk2, k);
-                    lt_best = top ? (uint32_t)lt : lt_best;
-                    lk = top ? k : lk;
+                if (s > 0) {
+                    lk = 0;
+                    lk2 = 0;
+                    lt_best = 0;
+                    for (int lt0 = 0; lt0 < ntl; lt0 += kWave) {
+                        const int lt = lt0 + lane;
+                        const unsigned long long kr = tkeyl[lt < ntl ? lt : 0];
+                        const unsigned long long k = lt < ntl ? kr : 0ull;
+                        const bool top = k > lk;
+                        lk2 = top ? lk : umax64(lk2, k);
+                        lt_best = top ? (uint32_t)lt : lt_best;
+                        lk = top ? k : lk;
+                    }
                 }
                 const unsigned long long bk = wave_max_u64(lk);
                 const unsigned long long hit = bk != 0 ? ballot64(lk == bk) : 0ull;
@@ -812,11 +850,11 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             // 64-bit words (q < 64, q >= 64), and its rank in key order
             // (larger keys, then equal keys listed before it: only repeats of
             // one point are equal).  For q < 64, lanes take q and
-            // wavefronts take i, two at a time, and one ballot gives a word;
-            // the few q >= 64 are taken the other way round (lanes take i,
-            // wavefronts share the q) so that no pass runs over a nearly empty
-            // chunk of lanes.  Every ballot is of a single comparison, so its
-            // lane mask is used as it is.
+            // wavefronts take i, kRankPerPass at a time, and one ballot gives
+            // a word; the few q >= 64 are taken the other way round (lanes
+            // take i, wavefronts share the q) so that no pass runs over a
+            // nearly empty chunk of lanes.  Every ballot is of a single
+            // comparison, so its lane mask is used as it is.
             const bool two = W > (uint32_t)kWave;  // some candidates are q >= 64
             const unsigned long long v0 = ballot64((uint32_t)lane < W);
             const unsigned long long v1 = ballot64((uint32_t)lane + kWave < W);
@@ -828,27 +866,32 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             {
                 uint32_t r0l = 0, r0h = 0, rrk = 0;
                 int t = 0;
-                for (uint32_t i = (uint32_t)wave; i < W; i += 2 * kWavesPerBlock, t += 2) {
-                    // two independent candidates per pass (the second may lie
-                    // past the list: its results are not kept)
-                    const uint32_t i2 = i + kWavesPerBlock < W ? i + kWavesPerBlock : i;
-                    const float4 qa = sh.lq[i], qb = sh.lq[i2];
-                    const unsigned long long ka = ((unsigned long long)__float_as_uint(qa.w) << 32) | sh.lkl[i];
-                    const unsigned long long kb = ((unsigned long long)__float_as_uint(qb.w) << 32) | sh.lkl[i2];
-                    const float da = sqdist(qa.x, qa.y, qa.z, q0.x, q0.y, q0.z);
-                    const float db = sqdist(qb.x, qb.y, qb.z, q0.x, q0.y, q0.z);
-                    const unsigned long long ga = ballot64(k0 > ka) & v0, gb = ballot64(k0 > kb) & v0;
-                    bool ba = da < qa.w, bb = db < qb.w;
-                    if (euclid) {
-                        ba = ba && sqrt_class_top(da) < qa.w;
-                        bb = bb && sqrt_class_top(db) < qb.w;
+                constexpr int kP = kRankPerPass;
+                for (uint32_t i = (uint32_t)wave; i < W; i += kP * kWavesPerBlock, t += kP) {
+                    // kP independent candidates per pass (the later ones may
+                    // lie past the list: their results are not kept)
+                    float4 qa[kP];
+                    unsigned long long ka[kP];
+#pragma unroll
+                    for (int u = 0; u < kP; ++u) {
+                        const uint32_t iu = i + u * kWavesPerBlock < W ? i + u * kWavesPerBlock : i;
+                        qa[u] = sh.lq[iu];
+                        ka[u] = ((unsigned long long)__float_as_uint(qa[u].w) << 32) | sh.lkl[iu];
                     }
-                    const unsigned long long ma = ballot64(ba) & ga, mb = ballot64(bb) & gb;
-                    // lane t keeps the results of this wavefront's t-th candidate
-                    const bool sa = lane == t, sb = lane == t + 1;
-                    r0l = sa ? (uint32_t)ma : sb ? (uint32_t)mb : r0l;
-                    r0h = sa ? (uint32_t)(ma >> 32) : sb ? (uint32_t)(mb >> 32) : r0h;
-                    rrk = sa ? (uint32_t)__popcll(ga) : sb ? (uint32_t)__popcll(gb) : rrk;
+#pragma unroll
+                    for (int u = 0; u < kP; ++u) {
+                        const float da = sqdist(qa[u].x, qa[u].y, qa[u].z, q0.x, q0.y, q0.z);
+                        const unsigned long long ga = ballot64(k0 > ka[u]) & v0;
+                        bool ba = da < qa[u].w;
+                        if (euclid)
+                            ba = ba && sqrt_class_top(da) < qa[u].w;
+                        const unsigned long long ma = ballot64(ba) & ga;
+                        // lane t keeps the results of this wavefront's t-th candidate
+                        const bool sa = lane == t + u;
+                        r0l = sa ? (uint32_t)ma : r0l;
+                        r0h = sa ? (uint32_t)(ma >> 32) : r0h;
+                        rrk = sa ? (uint32_t)__popcll(ga) : rrk;
+                    }
                 }
                 const uint32_t i = (uint32_t)wave + (uint32_t)kWavesPerBlock * (uint32_t)lane;
                 if (i < W) {
@@ -1133,13 +1176,14 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
 
         // =============== A: apply the round's picks to the true state ===============
         // Lanes take picks k and k + 64 (the second set only when the round
-        // has more than 64), wavefronts take tiles, four at a time so that
-        // their sphere data is in flight together.  A tile's test uses its
-        // current threshold (only its own update can lower it); the picks
+        // has more than 64), wavefronts take tiles, kApplyTiles at a time so
+        // that their sphere loads are in flight together.  A tile's test uses
+        // its current threshold (only its own update can lower it); the picks
         // that survive update the tile's points (the minimum over picks does
-        // not depend on their order).  Every load of the tests is
-        // unconditional (indices clamped, results masked), so their path has
-        // no branches.
+        // not depend on their order).  The sphere array is padded to whole
+        // passes with spheres that never pass, so the tests need no bounds
+        // and a pass branches only when some tile of it is hit: this loop is
+        // bound by the instructions one wavefront issues, not by LDS.
         {
             const int ka = lane < P ? lane : 0, kc = lane + kWave < P ? lane + kWave : 0;
             const float sax = pkx[ka], say = pky[ka], saz = pkz[ka];
@@ -1147,43 +1191,41 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             const unsigned long long kma = P >= kWave ? ~0ull : ((1ull << P) - 1ull);
             const unsigned long long kmc =
                 P >= 2 * kWave ? ~0ull : P > kWave ? ((1ull << (P - kWave)) - 1ull) : 0ull;
+            constexpr int kT = kApplyTiles;
+            constexpr int kStep = kT * kWavesPerBlock;
             auto pass = [&](auto two_c) {
                 constexpr bool TWO = decltype(two_c)::value;
-                for (int lt0 = 4 * wave; lt0 < ntl; lt0 += 4 * kWavesPerBlock) {
-                    unsigned long long ma[4], mc[4];
-                    float qx[4], qy[4], qz[4], qt[4];
+                for (int lt0 = kT * wave; lt0 < ntl; lt0 += kStep) {
+                    unsigned long long ma[kT], mc[kT];
+                    float4 sp[kT];
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int li = lt0 + v < ntl ? lt0 + v : lt0;
-                        const float4 sp = tsph[li];
-                        qx[v] = sp.x;
-                        qy[v] = sp.y;
-                        qz[v] = sp.z;
-                        qt[v] = sp.w;
-                    }
+                    for (int v = 0; v < kT; ++v)
+                        sp[v] = tsph[lt0 + v];  // in the padding past the tiles
+                    unsigned long long any = 0;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
+                    for (int v = 0; v < kT; ++v) {
                         const int lt = lt0 + v;
-                        const bool tin = lt < ntl;
-                        ma[v] = ballot64(!(sqdist(qx[v], qy[v], qz[v], sax, say, saz) >= qt[v])) & (tin ? kma : 0ull);
-                        mc[v] = TWO ? ballot64(!(sqdist(qx[v], qy[v], qz[v], scx, scy, scz) >= qt[v])) &
-                                          (tin ? kmc : 0ull)
+                        ma[v] = ballot64(!(sqdist(sp[v].x, sp[v].y, sp[v].z, sax, say, saz) >= sp[v].w)) & kma;
+                        mc[v] = TWO ? ballot64(!(sqdist(sp[v].x, sp[v].y, sp[v].z, scx, scy, scz) >= sp[v].w)) & kmc
                                     : 0ull;
-                        if (tele && lane == 0 && tin) {
+                        any |= ma[v] | mc[v];
+                        if (tele && lane == 0 && lt < ntl) {
                             const unsigned long long nh = (unsigned long long)(__popcll(ma[v]) + __popcll(mc[v]));
                             tl.tests += (unsigned long long)P;
                             tl.pruned += (unsigned long long)P - nh;
                             tl.visited += nh * (tmeta[lt] >> 16);
                         }
                     }
+                    if (!any)
+                        continue;
                     unsigned long long t_upd = 0;
-                    if (clocks && (ma[0] | ma[1] | ma[2] | ma[3] | mc[0] | mc[1] | mc[2] | mc[3])) {
+                    if (clocks) {
                         t_upd = wall_clock64();
-                        for (int v = 0; v < 4; ++v)
+                        for (int v = 0; v < kT; ++v)
                             tl.apairs += (unsigned long long)(__popcll(ma[v]) + __popcll(mc[v]));
                     }
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
+                    for (int v = 0; v < kT; ++v) {
                         if (!(ma[v] | mc[v]))
                             continue;
                         const int lt = lt0 + v;

@@ -97,20 +97,34 @@ class ParamModel:
         return nv, sh, k, y
 
 
+def fitting_default(n: int, ms) -> int:
+    """The default rule's candidate, or when its grid does not fit on chip
+    (ms not finite) the next coarser one-shell grid that does (candidates
+    run n_vox-major, the one-shell grid first)."""
+    cand = candidates()
+    d = default_candidate(n)
+    while not np.isfinite(ms[d]) and d > 0:
+        d -= 1
+        while d > 0 and cand[d][1] != 0.0:
+            d -= 1
+    return d
+
+
 def fps_auto(model: ParamModel, xyz: torch.Tensor, m: int, start: int = 0, **kw):
     """Exact FPS with the network's grid, falling back to the default rule
-    when the chosen grid does not fit on chip.  Returns (idx, d2, (n_vox, shell))."""
+    (and then to coarser one-shell grids) when a grid does not fit on chip.
+    Returns (idx, d2, (n_vox, shell))."""
     from . import RfpsError, fps
     nv, sh, _, _ = model.choose(xyz)
-    try:
-        i, d = fps(xyz, m, start, n_vox=nv, shell=sh, **kw)
-        return i, d, (nv, sh)
-    except RfpsError as e:
-        if e.status != 6:
-            raise
-    nv0 = default_n_vox(xyz.shape[0])
-    i, d = fps(xyz, m, start, n_vox=nv0, **kw)
-    return i, d, (nv0, 0.0)
+    grids = sorted({v for v, _ in candidates()}, reverse=True)
+    tries = [(nv, sh)] + [(v, 0.0) for v in grids if v <= default_n_vox(xyz.shape[0])]
+    for r, (v, s) in enumerate(tries):
+        try:
+            i, d = fps(xyz, m, start, n_vox=v, shell=s, **kw)
+            return i, d, (v, s)
+        except RfpsError as e:
+            if e.status != 6 or r + 1 == len(tries):
+                raise
 
 
 # ---------------------------------------------------------------------------
@@ -139,7 +153,9 @@ def sweep_cloud(x: torch.Tensor, m: int, idx=None, repeats: int = 1, prune_rates
     idx = build_index(x, n_vox=nv0, reuse=idx)
     sample(idx, m, 0, out_idx=out_i, out_d2=out_d)
     torch.cuda.synchronize()
-    ref = out_i.clone()
+    # every grid must give the same sequence; the reference is the first
+    # that fits on chip (the default may not: its status is then 6)
+    ref = out_i.clone() if read_status(idx) == 0 else None
     ms = np.zeros(MLP_CANDIDATES)
     prune = np.zeros(MLP_CANDIDATES)
     for k, (nv, sh) in enumerate(candidates()):
@@ -158,6 +174,8 @@ def sweep_cloud(x: torch.Tensor, m: int, idx=None, repeats: int = 1, prune_rates
                 break
         st = read_status(idx)
         if st == 0:
+            if ref is None:
+                ref = out_i.clone()
             if not torch.equal(out_i, ref):
                 raise RuntimeError("candidate %d changed the sampled sequence" % k)
             if prune_rates:
@@ -221,7 +239,7 @@ def evaluate(net, X, MS, N, margin):
     y = net.forward(torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(net.device)).cpu().numpy()
     rows = []
     for b in range(X.shape[0]):
-        d = default_candidate(int(N[b]))
+        d = fitting_default(int(N[b]), MS[b])
         pred = y[b, :MLP_CANDIDATES]
         k = int(np.argmin(pred))
         if not pred[k] < pred[d] - margin or not np.isfinite(MS[b, k]):
