@@ -460,8 +460,9 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 const float lx = px[p], ly = py[p], lz = pz[p];
                 // runner-up: the largest local key of any other point of this
                 // workgroup (other tiles, and the rest of the best tile); it
-                // bounds them if this candidate is not taken at its turn
-                unsigned long long ru = wave_max_u64(lk == bk ? lk2 : lk);
+                // bounds them if this candidate is not taken at its turn.  One
+                // reduction takes both parts.
+                unsigned long long ru;
                 {
                     const uint32_t meta = tmeta[bt];
                     const uint32_t ls = meta & 0xffffu, cnt = meta >> 16;
@@ -470,7 +471,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     const float dpl = pdl[pp], dpt = pd[pp];
                     const float dl = tflag[bt] ? dpl : dpt;
                     const unsigned long long k = valid ? pack_key(dl, po[pp]) : 0ull;
-                    ru = umax64(ru, wave_max_u64(k == bk ? 0ull : k));
+                    ru = wave_max_u64(umax64(lk == bk ? lk2 : lk, k == bk ? 0ull : k));
                 }
                 if (lane == 0) {
                     sh.my[6 * s + 0] = __float_as_uint(lx);
@@ -545,36 +546,25 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         {
             const int total = G * W;
             const unsigned long long *sbase = board + (size_t)(epoch & 1u) * G * kMaxSlotWords;
+            // Word r of this thread (e = tid + kBlock * r): word w = e % W of
+            // group g = e / W, and the LDS word it fills.  Field f of candidate
+            // w / 6 (x, y, z, local d2, index, runner-up d2) goes to the
+            // arrays cx, cy, cz, cld, corig, crun, which sit G * R words apart
+            // in that order; the bound key's halves (high first) to bkey.
             unsigned long long pend = 0;
+            uint32_t off[W];
+            uint32_t *dst[W];
 #pragma unroll
-            for (int r = 0; r < W; ++r)
-                pend |= (tid + kBlock * r < total) ? (1ull << r) : 0ull;
-            bool ab = false;
-            // stores one word of a slot into the candidate arrays; false while
-            // the word does not carry the round's epoch yet
-            auto take = [&](int r, unsigned long long xr) -> bool {
-                const uint32_t ep = (uint32_t)(xr >> 32);
-                ab |= ep == kAbortEpoch;
-                if (ep != epoch)
-                    return false;
-                const int e = tid + kBlock * r, g = e / W, w = e % W;
-                const uint32_t v = (uint32_t)xr;
-                if (w < 6 * R) {
-                    // field f of candidate w / 6: x, y, z, local d2, index,
-                    // runner-up d2; the arrays sit in LDS in that order (cx, cy,
-                    // cz, cld, corig, crun), G * R words apart
-                    const int f = w % 6;
-                    reinterpret_cast<uint32_t *>(cx)[f * (G * R) + g * R + w / 6] = v;
-                } else {
-                    // the bound key: high half first (little-endian halves)
-                    reinterpret_cast<uint32_t *>(bkey + g * (R + 1) + R)[w == 6 * R ? 1 : 0] = v;
-                }
-                return true;
-            };
-            auto word = [&](int r) {
+            for (int r = 0; r < W; ++r) {
                 const int e = tid + kBlock * r;
-                return sbase + (size_t)(e / W) * kMaxSlotWords + e % W;
-            };
+                const bool in = e < total;
+                const int g = in ? e / W : 0, w = in ? e % W : 0;
+                pend |= in ? (1ull << r) : 0ull;
+                off[r] = (uint32_t)(g * kMaxSlotWords + w);
+                dst[r] = w < 6 * R ? reinterpret_cast<uint32_t *>(cx) + ((w % 6) * (G * R) + g * R + w / 6)
+                                   : reinterpret_cast<uint32_t *>(bkey + g * (R + 1) + R) + (w == 6 * R ? 1 : 0);
+            }
+            bool ab = false;
             constexpr int kFast = W < 32 ? W : 32;
             unsigned long long t_first = 0;
             for (uint32_t spin = 0; pend && !ab && spin < kSpinLimit; ++spin) {
@@ -587,13 +577,21 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
 #pragma unroll
                     for (int q = 0; q < kFast; ++q) {
                         const int r = r0 + q;
-                        x[q] = (r < W && ((pend >> r) & 1ull)) ? bload<S>(word(r)) : 0ull;
+                        x[q] = (r < W && ((pend >> r) & 1ull)) ? bload<S>(sbase + off[r]) : 0ull;
                     }
+                    // a word is taken once it carries the round's epoch (a
+                    // word not read this pass is 0, and epochs start at 1)
 #pragma unroll
                     for (int q = 0; q < kFast; ++q) {
                         const int r = r0 + q;
-                        if (r < W && ((pend >> r) & 1ull) && take(r, x[q]))
-                            pend &= ~(1ull << r);
+                        if (r >= W)
+                            break;
+                        const uint32_t ep = (uint32_t)(x[q] >> 32);
+                        ab |= ep == kAbortEpoch;
+                        const bool ok = ep == epoch;
+                        if (ok)
+                            *dst[r] = (uint32_t)x[q];
+                        pend &= ok ? ~(1ull << r) : ~0ull;
                     }
                 }
             }
