@@ -11,17 +11,19 @@
 //
 //   L  lookahead: every workgroup runs R steps of FPS on its own points only
 //      (on the private copy, with the same spherical pruning), giving local
-//      candidates l_1..l_R with local keys k_1 > .. > k_R, the bound
-//      k_{R+1} (the largest local key left after them), and for every step h
-//      the runner-up u_h, the largest local key of the group's other points
-//      when l_h was chosen;
+//      candidates l_1..l_R with local keys k_1 > .. > k_R, and for every step
+//      h the runner-up u_h, the largest local key of the group's other points
+//      when l_h was chosen.  The group's bound k_{R+1} = max(u_R, (0, l_R))
+//      is at least every local key once l_R is applied too (applying it only
+//      lowers the others, and its own distance becomes 0), so that last
+//      update is never run;
 //   X  exchange: each workgroup publishes its candidates (coordinates, local
 //      distance, original index, runner-up distance) and k_{R+1};
 //   M  merge: every workgroup replays the same deterministic merge.  Group g
 //      keeps a head h_g (how many of its candidates were taken).  Its bound
-//      B_g = k_{h_g+1} is an upper bound on the true key of every point of g:
-//      the true distances include every pick of the round so far, among them
-//      l_1..l_{h_g}, so they are at most the local ones.  Hence the largest
+//      B_g = k_{h_g+1} is an upper bound on the true key of every point of g
+//      not taken: the true distances include every pick of the round so far,
+//      among them l_1..l_{h_g}, so they are at most the local ones.  Hence the largest
 //      true key anywhere is at most max_g B_g, and if the head candidate of
 //      the group with the largest bound still has its true key equal to its
 //      local key (no other pick of the round lowered it), that candidate is
@@ -421,7 +423,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 tl.sub[4] += t - t_mark;
                 tl.sub[5] -= t;  // the steps end at the phase mark below
             }
-            for (int s = 0; s <= R; ++s) {
+            for (int s = 0; s < R; ++s) {
                 // arg max over the local tile keys (key and tile travel
                 // together; step 0's was taken with the copy)
                 if (clocks)
@@ -442,15 +444,12 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 }
                 const unsigned long long bk = wave_max_u64(lk);
                 const unsigned long long hit = bk != 0 ? ballot64(lk == bk) : 0ull;
-                if (s == R || bk == 0) {
-                    // the bound (or an empty workgroup): no more local candidates
-                    if (lane == 0) {
-                        sh.my[6 * R] = (uint32_t)(bk >> 32);
-                        sh.my[6 * R + 1] = (uint32_t)bk;
-                        for (int q = s; q < R; ++q)
-                            for (int w = 0; w < 6; ++w)
-                                sh.my[6 * q + w] = 0;
-                    }
+                if (bk == 0) {
+                    // a workgroup without points: bound 0, no candidates
+                    // (every point's key is above 0, so this is step 0)
+                    if (lane == 0)
+                        for (int w = 0; w < W; ++w)
+                            sh.my[w] = 0;
                     if (clocks)
                         tl.sub[9] += wall_clock64();
                     break;
@@ -480,9 +479,17 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     sh.my[6 * s + 3] = (uint32_t)(bk >> 32);  // local d2
                     sh.my[6 * s + 4] = po[p];
                     sh.my[6 * s + 5] = (uint32_t)(ru >> 32);  // runner-up d2
+                    if (s == R - 1) {
+                        // the bound: the runner-up, or l_R itself at distance 0
+                        const unsigned long long b = umax64(ru, pack_key(0.0f, po[p]));
+                        sh.my[6 * R] = (uint32_t)(b >> 32);
+                        sh.my[6 * R + 1] = (uint32_t)b;
+                    }
                 }
                 if (clocks)
                     tl.sub[9] += wall_clock64();
+                if (s == R - 1)
+                    break;  // l_R is not applied to the private copy
                 // local update with l_s (pruned against the local thresholds)
                 for (int lt0 = 0; lt0 < ntl; lt0 += kWave) {
                     const int lt = lt0 + lane;

@@ -50,8 +50,10 @@ def key(d, o):
     return (fbits(d) << 32) | ((~int(o)) & 0xffffffff)
 
 
-def run(P, m, start, G, R, klist=128):
+def run(P, m, start, G, R, klist=128, bound="runner"):
     """FPS of m points from start with G groups of R candidates per round.
+    A group's bound is the runner-up of its last step (bound="runner"), or
+    the largest local key after all R steps (bound="next").
     Returns (indices, distances, rounds, failures)."""
     n = len(P)
     groups = [np.arange(g, n, G) for g in range(G)]
@@ -78,12 +80,17 @@ def run(P, m, start, G, R, klist=128):
                 others = keys[:t] + keys[t + 1:]
                 runner = max(others) if others else 0
                 cands[g * R + s] = (idx[t], Dl[t], runner >> 32)
+                if bound == "runner" and s == R - 1:
+                    # applying l_R only lowers the other points' keys, and
+                    # its own becomes (0, its index)
+                    bounds[g] = max(runner, key(0.0, idx[t]))
+                    break
                 dd = d2(P[idx], P[idx[t]])
                 Dl = np.where(dd < Dl, dd, Dl).astype(f32)
-        bkey = {c: (0 if bounds[c // R] == 0 or c not in cands else key(cands[c][1], cands[c][0]))
-                for c in range(G * R)}
+        bkey = {c: (key(cands[c][1], cands[c][0]) if c in cands else 0) for c in range(G * R)}
         smax = max(bounds.values())
-        lst = [c for c in range(G * R) if bkey[c] > smax or (bkey[c] == smax and bounds[c // R] == smax)]
+        lst = [c for c in range(G * R)
+               if bkey[c] != 0 and (bkey[c] > smax or (bkey[c] == smax and bounds[c // R] == smax))]
         scur = smax
         if len(lst) > klist:
             srt = sorted(lst, key=lambda c: (-bkey[c], lst.index(c)))
