@@ -129,7 +129,7 @@ __host__ __device__ __forceinline__ uint32_t padded_tiles(uint32_t tiles)
 
 __host__ __device__ __forceinline__ uint32_t rounds_lds_need(uint32_t tiles, uint32_t pts, uint32_t G, uint32_t R)
 {
-    return tiles * 40u + padded_tiles(tiles) * 16u + pts * 24u + G * R * 24u + G * (R + 1u) * 8u +
+    return tiles * 40u + padded_tiles(tiles) * 16u + pts * 24u + G * (6u * R + 2u) * 4u + G * (R + 1u) * 8u +
            sort_cap(G, R) * 4u + merge_words(G, R) * 4u + 128u;
 }
 
@@ -211,7 +211,9 @@ struct RoundShared {
     uint32_t abort, list_n, npick, mcount, pfront, pback, mtotal, msel;
     float4 lq[kList];                   // merge: listed candidates' coordinates and listed distance
     uint32_t lkl[kList];                // merge: low halves of their keys (~ original index)
-    unsigned long long lset[kList][2];  // merge: listed candidates with larger keys that would lower each one
+    // merge: listed candidates with larger keys that would lower each one
+    // (positions below 64, and 64 and up)
+    unsigned long long lset0[kList], lset1[kList];
     uint32_t lrank[kList];              // merge: rank of each listed candidate in key order
     uint32_t repw[kWavesPerBlock];      // merge: a wavefront's groups repeat a candidate (equal keys)
     uint32_t hist[256];    // merge: candidates per key bucket
@@ -267,9 +269,11 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
     // ---- LDS layout (the plan checked that it fits) ----
     unsigned long long *tkey = reinterpret_cast<unsigned long long *>(smem);
     unsigned long long *tkeyl = tkey + ntl;
-    unsigned long long *bkey = tkeyl + ntl;  // [G][R+1] published local keys
+    // order of a cut list (kList + 1 words; a list is cut only when G * R >
+    // kList, and then this holds 2 G (R + 1) > kList words)
+    unsigned long long *obuf = tkeyl + ntl;
     // merge: the keys in sort order, then (same memory) the pick coordinates
-    unsigned long long *skey = bkey + (size_t)G * (R + 1);
+    unsigned long long *skey = obuf + (size_t)G * (R + 1);
     float *pkx = reinterpret_cast<float *>(skey);
     float *pky = pkx + kMaxRoundPicks;
     float *pkz = pky + kMaxRoundPicks;
@@ -289,13 +293,13 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
     uint32_t *tbest = tmeta + ntl;
     uint32_t *tbestl = tbest + ntl;
     uint32_t *tflag = tbestl + ntl;
-    float *cx = reinterpret_cast<float *>(tflag + ntl);  // [G][R] candidates
-    float *cy = cx + G * R;
-    float *cz = cy + G * R;
-    float *cld = cz + G * R;  // local d2 (the selection d2 of a certified candidate)
-    uint32_t *corig = reinterpret_cast<uint32_t *>(cld + G * R);
-    uint32_t *crun = corig + G * R;  // distance bits of the runner-up at the candidate's lookahead step
-    uint32_t *sidx = crun + G * R;  // merge order; its first P entries are the round's picks
+    // the round's slots as published, one W-word image per group: candidate
+    // s of group g is x, y, z, local d2, original index and runner-up d2 at
+    // words 6 s .. 6 s + 5, the bound key's high and low halves follow
+    uint32_t *simg = reinterpret_cast<uint32_t *>(tflag + ntl);
+    // field f of candidate c = g * R + s
+    auto cword = [&](uint32_t c, int f) -> uint32_t { return simg[(c / R) * W + 6 * (c % R) + f]; };
+    uint32_t *sidx = simg + G * W;  // merge order; its first P entries are the round's picks
     float *px = reinterpret_cast<float *>(sidx + sort_cap(G, R));
 
     // ---- prologue: tile metadata and LDS offsets (block prefix sum) ----
@@ -553,23 +557,17 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         {
             const int total = G * W;
             const unsigned long long *sbase = board + (size_t)(epoch & 1u) * G * kMaxSlotWords;
-            // Word r of this thread (e = tid + kBlock * r): word w = e % W of
-            // group g = e / W, and the LDS word it fills.  Field f of candidate
-            // w / 6 (x, y, z, local d2, index, runner-up d2) goes to the
-            // arrays cx, cy, cz, cld, corig, crun, which sit G * R words apart
-            // in that order; the bound key's halves (high first) to bkey.
+            // Word r of this thread, e = tid + kBlock * r, is word e % W of
+            // group e / W's slot; it goes to word e of the slot image, so the
+            // lanes of a wavefront store to neighbouring LDS words.
             unsigned long long pend = 0;
             uint32_t off[W];
-            uint32_t *dst[W];
 #pragma unroll
             for (int r = 0; r < W; ++r) {
                 const int e = tid + kBlock * r;
                 const bool in = e < total;
-                const int g = in ? e / W : 0, w = in ? e % W : 0;
                 pend |= in ? (1ull << r) : 0ull;
-                off[r] = (uint32_t)(g * kMaxSlotWords + w);
-                dst[r] = w < 6 * R ? reinterpret_cast<uint32_t *>(cx) + ((w % 6) * (G * R) + g * R + w / 6)
-                                   : reinterpret_cast<uint32_t *>(bkey + g * (R + 1) + R) + (w == 6 * R ? 1 : 0);
+                off[r] = in ? (uint32_t)((e / W) * kMaxSlotWords + e % W) : 0u;
             }
             bool ab = false;
             constexpr int kFast = W < 32 ? W : 32;
@@ -597,7 +595,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                         ab |= ep == kAbortEpoch;
                         const bool ok = ep == epoch;
                         if (ok)
-                            *dst[r] = (uint32_t)x[q];
+                            simg[tid + kBlock * r] = (uint32_t)x[q];
                         pend &= ok ? ~(1ull << r) : ~0ull;
                     }
                 }
@@ -619,13 +617,13 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         unsigned long long gbound = 0;
         if (!sh.abort) {
             const int g = tid < G ? tid : 0;
-            gbound = tid < G ? bkey[g * (R + 1) + R] : 0ull;
+            const uint32_t *gi = simg + g * W;
+            gbound = tid < G ? ((unsigned long long)gi[6 * R] << 32) | gi[6 * R + 1] : 0ull;
             const bool empty = gbound == 0ull;
             bool repeat = false;
 #pragma unroll
             for (int s2 = 0; s2 < R; ++s2) {
-                const int c = g * R + s2;
-                gkey[s2] = empty ? 0ull : ((unsigned long long)__float_as_uint(cld[c]) << 32) | (~corig[c]);
+                gkey[s2] = empty ? 0ull : ((unsigned long long)gi[6 * s2 + 3] << 32) | (~gi[6 * s2 + 4]);
                 if (s2 > 0)
                     repeat = repeat || (gkey[s2] == gkey[s2 - 1] && gkey[s2] != 0ull);
             }
@@ -696,9 +694,10 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             const unsigned long long below = lane ? (~0ull >> (kWave - lane)) : 0ull;
             // what the ranking pass reads about listed candidate pos (candidate c, key k)
             auto stage = [&](uint32_t pos, uint32_t c, unsigned long long k) {
-                sh.lq[pos] = make_float4(cx[c], cy[c], cz[c], __uint_as_float((uint32_t)(k >> 32)));
+                sh.lq[pos] = make_float4(__uint_as_float(cword(c, 0)), __uint_as_float(cword(c, 1)),
+                                         __uint_as_float(cword(c, 2)), __uint_as_float((uint32_t)(k >> 32)));
                 sh.lkl[pos] = (uint32_t)k;
-                sh.lset[pos][1] = 0ull;
+                sh.lset1[pos] = 0ull;
                 sh.lrank[pos] = 0u;
             };
 #pragma unroll
@@ -722,7 +721,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             __syncthreads();
             const uint32_t L = sh.mcount;
             const bool rep = (sh.repw[0] | sh.repw[1] | sh.repw[2] | sh.repw[3]) != 0u;
-            uint32_t *ord = reinterpret_cast<uint32_t *>(bkey);  // bkey is not read again this round
+            uint32_t *ord = reinterpret_cast<uint32_t *>(obuf);
             // scur: every listed key is above it (or equals S*, see taken) and
             // every point left out of the list has its true key at most it
             unsigned long long scur = smax;
@@ -854,11 +853,12 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             // value of their distance below i's listed distance), as two
             // 64-bit words (q < 64, q >= 64), and its rank in key order
             // (larger keys, then equal keys listed before it: only repeats of
-            // one point are equal).  For q < 64, lanes take q and
-            // wavefronts take i, kRankPerPass at a time, and one ballot gives
-            // a word; the few q >= 64 are taken the other way round (lanes
-            // take i, wavefronts share the q) so that no pass runs over a
-            // nearly empty chunk of lanes.  Every ballot is of a single
+            // one point are equal).  For q < 64, lanes take q and the
+            // wavefronts take every fourth i, kRankPerPass at a time (measured
+            // faster than a contiguous quarter of the list each), and one
+            // ballot gives a word; the few q >= 64 are taken the other way
+            // round (lanes take i, wavefronts share the q) so that no pass
+            // runs over a nearly empty chunk of lanes.  Every ballot is of a single
             // comparison, so its lane mask is used as it is.
             const bool two = W > (uint32_t)kWave;  // some candidates are q >= 64
             const unsigned long long v0 = ballot64((uint32_t)lane < W);
@@ -900,7 +900,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 }
                 const uint32_t i = (uint32_t)wave + (uint32_t)kWavesPerBlock * (uint32_t)lane;
                 if (i < W) {
-                    sh.lset[i][0] = ((unsigned long long)r0h << 32) | r0l;
+                    sh.lset0[i] = ((unsigned long long)r0h << 32) | r0l;
                     atomicAdd(&sh.lrank[i], rrk);
                 }
             }
@@ -928,12 +928,12 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                 }
                 if ((uint32_t)lane < W) {
                     if (s0)
-                        atomicOr(&sh.lset[lane][1], s0);
+                        atomicOr(&sh.lset1[lane], s0);
                     atomicAdd(&sh.lrank[lane], c0);
                 }
                 if ((uint32_t)lane + kWave < W) {
                     if (s1)
-                        atomicOr(&sh.lset[lane + kWave][1], s1);
+                        atomicOr(&sh.lset1[lane + kWave], s1);
                     atomicAdd(&sh.lrank[lane + kWave], c1);
                 }
             }
@@ -967,9 +967,9 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             // the largest key, and the picks before it are the live
             // candidates with larger keys, which stay live from then on.
             if (wave == 0) {
-                unsigned long long s00 = sh.lset[lane][0], s01 = sh.lset[lane][1];
-                unsigned long long s10 = two ? sh.lset[lane + kWave][0] : 0ull;
-                unsigned long long s11 = two ? sh.lset[lane + kWave][1] : 0ull;
+                unsigned long long s00 = sh.lset0[lane], s01 = sh.lset1[lane];
+                unsigned long long s10 = two ? sh.lset0[lane + kWave] : 0ull;
+                unsigned long long s11 = two ? sh.lset1[lane + kWave] : 0ull;
                 const uint32_t rk0 = sh.lrank[lane], rk1 = two ? sh.lrank[lane + kWave] : 0u;
                 const uint32_t cc0 = sidx[lane], cc1 = two ? sidx[lane + kWave] : 0u;
                 unsigned long long kc0 = k0, kc1 = k1;      // current listed keys
@@ -1018,7 +1018,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                         tv = min_dist(tv, d1, euclid);
                     const float tf = fminf(wave_min_dist(tv), __uint_as_float((uint32_t)(kf >> 32)));
                     const unsigned long long kt = ((unsigned long long)__float_as_uint(tf) << 32) | (uint32_t)kf;
-                    scur = umax64(scur, ((unsigned long long)crun[cf] << 32) | 0xffffffffull);
+                    scur = umax64(scur, ((unsigned long long)cword(cf, 5) << 32) | 0xffffffffull);
                     const uint32_t gf = cf / R, hf = cf % R;
                     // the group's later candidates (their local keys assumed
                     // this one picked) and every key <= the bound leave; the
@@ -1073,8 +1073,6 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                             s01 = n1;
                         }
                     }
-                    if (lane == 0)
-                        cld[cf] = tf;  // its listed (and, once certified, output) distance
                 }
                 // Order of the live candidates by current key.  A candidate
                 // whose key never changed has its list rank less the

@@ -253,6 +253,42 @@ def evaluate(net, X, MS, N, margin):
     return {"gain_vs_default": gain, "regret_vs_best": regret, "best_vs_default": headroom, "clouds": rows}
 
 
+def report_markdown(report: dict, command: str) -> str:
+    """The evaluation as a markdown summary (held-out clouds listed one by one)."""
+    def grid(k):
+        nv, sh = mlp_candidate(k)
+        return "n_vox %d, %s" % (nv, "one shell" if sh == 0.0 else "%g m" % sh)
+
+    out = ["# Voxel-parameter network: evaluation on held-out clouds", "",
+           "Sweep, training and evaluation by `paper_2606_06255_amd/param_model.py` on one MI355X.",
+           "Every time is the median of %d timed runs of build + sample (M = N/4; M = 65,536 for the dense"
+           % report["repeats"],
+           "LiDAR cloud) with the given grid and the library's default sampler settings, HIP events, after a",
+           "warm-up run; every grid was checked to give the same selections as the first grid that fits on chip.",
+           "A default grid that does not fit counts as the next coarser one-shell grid that does.", "",
+           "Command (from the repository root on the GPU host):", "", "```", command, "```", "",
+           "Training: %d clouds, full-batch Adam on the GPU (library kernels), %d steps, lr %g; choice margin "
+           "%g (log units). Final training loss %.4f." % (report["train_clouds"], report["steps"], report["lr"],
+                                                         report["margin"], report["loss"][-1][1]), "",
+           "Gains are geometric means over clouds of time(default rule) / time(choice); 'best' is the",
+           "fastest of the 36 measured grids (the grid search), so best/default is the headroom.", "",
+           "| set | clouds | network vs default | network regret vs best | best vs default |",
+           "|---|---:|---:|---:|---:|"]
+    names = {"train": "training clouds", "heldout": "held-out clouds", "dense_lidar_1M": "dense LiDAR, N = 1,048,576"}
+    for k in ("train", "heldout", "dense_lidar_1M"):
+        r = report[k]
+        out.append("| %s | %d | %.3fx | %.3fx | %.3fx |" % (names[k], len(r["clouds"]), r["gain_vs_default"],
+                                                         r["regret_vs_best"], r["best_vs_default"]))
+    c = report["dense_lidar_1M"]["clouds"][0]
+    out += ["", "Dense LiDAR cloud: default %s %.2f ms; network %s %.2f ms; best %s %.2f ms." % (
+        grid(c["default"]), c["ms_default"], grid(c["choice"]), c["ms_choice"], grid(c["best"]), c["ms_best"]),
+        "", "Held-out clouds:", "", "| N | default | ms | network choice | ms | best ms |", "|---:|---|---:|---|---:|---:|"]
+    for c in report["heldout"]["clouds"]:
+        out.append("| %d | %s | %.2f | %s | %.2f | %.2f |" % (c["n"], grid(c["default"]), c["ms_default"],
+                                                             grid(c["choice"]), c["ms_choice"], c["ms_best"]))
+    return "\n".join(out) + "\n"
+
+
 def cloud_sizes(seed: int, total: int, n_min: int, n_max: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return np.floor(np.exp(rng.uniform(math.log(n_min), math.log(n_max), total))).astype(np.int64)
@@ -336,7 +372,7 @@ def main(argv=None):
         if not np.array_equal(I[order], np.arange(total + 1)):
             raise SystemExit("parts do not cover clouds 0..%d exactly once" % total)
         out = {k: np.concatenate([d[k] for d in parts])[order] for k in ("X", "MS", "PR", "N")}
-        np.savez(os.path.join(args.out, "sweep.npz"), I=I[order], **out)
+        np.savez_compressed(os.path.join(args.out, "sweep.npz"), I=I[order], **out)
         log("merged %d clouds into %s" % (I.size, os.path.join(args.out, "sweep.npz")))
         return 0
 
@@ -380,6 +416,9 @@ def main(argv=None):
     np.savez(os.path.join(args.out, "param_mlp.npz"), params=params, margin=np.float32(args.margin))
     with open(os.path.join(args.out, "param_report.json"), "w") as f:
         json.dump(report, f, indent=1)
+    with open(os.path.join(args.out, "param_model_evaluation.md"), "w") as f:
+        f.write(report_markdown(report, "python3 -m paper_2606_06255_amd.param_model " + " ".join(
+            sys.argv[1:] if argv is None else argv)))
     return 0
 
 
