@@ -80,6 +80,9 @@ struct RoundArgs {
 // (the merge stops there; a shorter round is always valid).
 constexpr int kList = 2 * kWave;
 constexpr int kMaxRoundPicks = kList;
+// Words of the order of a cut list (kList + 1, rounded to whole 8-byte words).
+constexpr uint32_t kOrdWords = kList + 2;
+
 // Tiles a wavefront tests per pass of the apply phase (their sphere loads are
 // in flight together; 8 measured faster than 4 or 16).
 constexpr int kApplyTiles = 8;
@@ -129,7 +132,7 @@ __host__ __device__ __forceinline__ uint32_t padded_tiles(uint32_t tiles)
 
 __host__ __device__ __forceinline__ uint32_t rounds_lds_need(uint32_t tiles, uint32_t pts, uint32_t G, uint32_t R)
 {
-    return tiles * 40u + padded_tiles(tiles) * 16u + pts * 24u + G * (6u * R + 2u) * 4u + G * (R + 1u) * 8u +
+    return tiles * 40u + padded_tiles(tiles) * 16u + pts * 24u + G * (6u * R + 2u) * 4u + kOrdWords * 4u +
            sort_cap(G, R) * 4u + merge_words(G, R) * 4u + 128u;
 }
 
@@ -269,11 +272,9 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
     // ---- LDS layout (the plan checked that it fits) ----
     unsigned long long *tkey = reinterpret_cast<unsigned long long *>(smem);
     unsigned long long *tkeyl = tkey + ntl;
-    // order of a cut list (kList + 1 words; a list is cut only when G * R >
-    // kList, and then this holds 2 G (R + 1) > kList words)
-    unsigned long long *obuf = tkeyl + ntl;
+    unsigned long long *obuf = tkeyl + ntl;  // order of a cut list
     // merge: the keys in sort order, then (same memory) the pick coordinates
-    unsigned long long *skey = obuf + (size_t)G * (R + 1);
+    unsigned long long *skey = obuf + kOrdWords / 2;
     float *pkx = reinterpret_cast<float *>(skey);
     float *pky = pkx + kMaxRoundPicks;
     float *pkz = pky + kMaxRoundPicks;
