@@ -208,10 +208,9 @@ __device__ __forceinline__ unsigned long long bload(const unsigned long long *p)
 // Scalars every workgroup keeps in LDS (static shared memory of the kernels).
 struct RoundShared {
     unsigned long long red[kWavesPerBlock];
-    uint32_t redi[kWavesPerBlock];
     uint32_t scan[kWavesPerBlock];
     unsigned long long red2[kWavesPerBlock];
-    uint32_t abort, list_n, npick, mcount, pfront, pback, mtotal, msel;
+    uint32_t abort, npick, mcount, pfront, mtotal, msel;
     float4 lq[kList];                   // merge: listed candidates' coordinates and listed distance
     uint32_t lkl[kList];                // merge: low halves of their keys (~ original index)
     // merge: listed candidates with larger keys that would lower each one
@@ -378,10 +377,8 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             }
             tile_rekey<4>(lane, lt, ls, c, dp, op, trad, tkey, tbest, tthr);
         }
-        if (tid == 0) {
-            sh.list_n = 0;
+        if (tid == 0)
             sh.abort = 0;
-        }
         __syncthreads();
     }
 
@@ -629,17 +626,14 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                     repeat = repeat || (gkey[s2] == gkey[s2 - 1] && gkey[s2] != 0ull);
             }
             const unsigned long long sk = wave_max_u64(gbound);
-            const unsigned long long hk = wave_max_u64(gkey[0]);
             const bool anyrep = ballot64(repeat) != 0ull;
             if (lane == 0) {
                 sh.red[wave] = sk;
-                sh.red2[wave] = hk;
                 sh.repw[wave] = anyrep ? 1u : 0u;
             }
             if (tid == 0) {
                 sh.mcount = 0;
                 sh.pfront = 0;
-                sh.pback = 0;
             }
         }
         __syncthreads();
@@ -678,12 +672,10 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         // between candidates do not change, so only the re-listed candidate's
         // own set is computed again, against its new key.
         {
-            unsigned long long smax = 0, hmax = 0;
+            unsigned long long smax = 0;
 #pragma unroll
-            for (int q = 0; q < kWavesPerBlock; ++q) {
+            for (int q = 0; q < kWavesPerBlock; ++q)
                 smax = umax64(smax, sh.red[q]);
-                hmax = umax64(hmax, sh.red2[q]);
-            }
             // Keys of different points differ, so only a group's own repeats
             // can tie: once every point of a group has local distance 0, its
             // lookahead returns its lowest index again and again, and its
@@ -729,13 +721,23 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
             uint32_t W = L;  // the list: skey / sidx [0, W)
             if (L > (uint32_t)kList) {
                 // a histogram of the keys' high halves (distance bits, between
-                // S* and the largest key) in 256 buckets
+                // S* and the largest listed key) in 256 buckets
+                unsigned long long hm = 0;
+                for (uint32_t i = tid; i < L; i += kBlock)
+                    hm = umax64(hm, skey[i]);
+                hm = wave_max_u64(hm);
+                if (lane == 0)
+                    sh.red2[wave] = hm;
+                sh.hist[tid] = 0;
+                __syncthreads();
+                unsigned long long hmax = 0;
+#pragma unroll
+                for (int q = 0; q < kWavesPerBlock; ++q)
+                    hmax = umax64(hmax, sh.red2[q]);
                 const uint32_t hlo = (uint32_t)(smax >> 32);
                 const uint32_t span = (uint32_t)(hmax >> 32) - hlo;
                 const int bits = span ? 32 - __clz((int)span) : 0;
                 const int bshift = bits > 8 ? bits - 8 : 0;
-                sh.hist[tid] = 0;
-                __syncthreads();
                 for (uint32_t i = tid; i < L; i += kBlock)
                     atomicAdd(&sh.hist[((uint32_t)(skey[i] >> 32) - hlo) >> bshift], 1u);
                 __syncthreads();
@@ -1287,8 +1289,6 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         if (clocks)
             tl.sub[8] += wall_clock64() - t_mark;
         __syncthreads();
-        if (tid == 0)
-            sh.list_n = 0;
         if (clocks)
             tl.ph[3] += wall_clock64() - t_mark;
     }
