@@ -391,46 +391,140 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
         if (clocks)
             t_mark = wall_clock64();
         // =============== L: local lookahead on a private copy ===============
-        // One wavefront runs the whole lookahead: the per-step reductions stay
+        // One wavefront runs the lookahead: the per-step reductions stay
         // inside it and its LDS operations complete in order, so the steps
         // need no workgroup barrier.  Lanes take tiles for the arg max and the
         // sphere tests; a tile that the test keeps is updated by all lanes.
-        if (wave == 0) {
-            // The private tile state starts from the true one; the first
-            // step's arg max over the tile keys is taken on the way.
+        // The first step reads the true tile state, while the other
+        // wavefronts copy it to the private state the later steps use.
+        {
             unsigned long long lk = 0, lk2 = 0;  // the lane's two largest tile keys
             uint32_t lt_best = 0;
-            // same trip count on every lane, loads clamped: no branches
-            for (int lt0 = 0; lt0 < ntl; lt0 += kWave) {
-                const int lt = lt0 + lane;
-                const bool tin = lt < ntl;
-                const int li = tin ? lt : 0;
-                const unsigned long long kr = tkey[li];
-                const float th = tsph[li].w;
-                const uint32_t tb = tbest[li];
-                if (tin) {
-                    tkeyl[lt] = kr;
-                    tthrl[lt] = th;
-                    tbestl[lt] = tb;
+            float lx = 0.0f, ly = 0.0f, lz = 0.0f;  // the last candidate
+            bool more = false;                     // the lookahead goes on after step 0
+            // candidate s from the lane maxima (lk, lk2, lt_best): its
+            // coordinates, local key, runner-up and, for the last, the bound;
+            // false for a workgroup without points
+            auto select = [&](int s, bool first) -> bool {
+                if (clocks)
+                    tl.sub[9] -= wall_clock64();
+                const unsigned long long bk = wave_max_u64(lk);
+                if (bk == 0) {
+                    // no points: bound 0, no candidates (every point's key is
+                    // above 0, so this is step 0)
+                    if (lane == 0)
+                        for (int w = 0; w < W; ++w)
+                            sh.my[w] = 0;
+                    if (clocks)
+                        tl.sub[9] += wall_clock64();
+                    return false;
+                }
+                const unsigned long long hit = ballot64(lk == bk);
+                const uint32_t bt = (uint32_t)__builtin_amdgcn_readlane((int)lt_best, __ffsll((long long)hit) - 1);
+                const uint32_t p = first ? tbest[bt] : tbestl[bt];
+                lx = px[p];
+                ly = py[p];
+                lz = pz[p];
+                // runner-up: the largest local key of any other point of this
+                // workgroup (other tiles, and the rest of the best tile); it
+                // bounds them if this candidate is not taken at its turn.  One
+                // reduction takes both parts.
+                unsigned long long ru;
+                {
+                    const uint32_t meta = tmeta[bt];
+                    const uint32_t ls = meta & 0xffffu, cnt = meta >> 16;
+                    const bool valid = (uint32_t)lane < cnt;
+                    const uint32_t pp = ls + (valid ? lane : 0);
+                    const float dpl = pdl[pp], dpt = pd[pp];
+                    const float dl = (!first && tflag[bt]) ? dpl : dpt;
+                    const unsigned long long k = valid ? pack_key(dl, po[pp]) : 0ull;
+                    ru = wave_max_u64(umax64(lk == bk ? lk2 : lk, k == bk ? 0ull : k));
+                }
+                if (lane == 0) {
+                    sh.my[6 * s + 0] = __float_as_uint(lx);
+                    sh.my[6 * s + 1] = __float_as_uint(ly);
+                    sh.my[6 * s + 2] = __float_as_uint(lz);
+                    sh.my[6 * s + 3] = (uint32_t)(bk >> 32);  // local d2
+                    sh.my[6 * s + 4] = po[p];
+                    sh.my[6 * s + 5] = (uint32_t)(ru >> 32);  // runner-up d2
+                    if (s == R - 1) {
+                        // the bound: the runner-up, or l_R itself at distance
+                        // 0 (l_R is never applied to the private copy)
+                        const unsigned long long b = umax64(ru, pack_key(0.0f, po[p]));
+                        sh.my[6 * R] = (uint32_t)(b >> 32);
+                        sh.my[6 * R + 1] = (uint32_t)b;
+                    }
+                }
+                if (clocks)
+                    tl.sub[9] += wall_clock64();
+                return true;
+            };
+            if (wave == 0) {
+                // same trip count on every lane, loads clamped: no branches
+                for (int lt0 = 0; lt0 < ntl; lt0 += kWave) {
+                    const int lt = lt0 + lane;
+                    const unsigned long long kr = tkey[lt < ntl ? lt : 0];
+                    const unsigned long long k = lt < ntl ? kr : 0ull;
+                    const bool top = k > lk;
+                    lk2 = top ? lk : umax64(lk2, k);
+                    lt_best = top ? (uint32_t)lt : lt_best;
+                    lk = top ? k : lk;
+                }
+                more = select(0, true) && R > 1;
+            } else {
+                for (int lt = tid - kWave; lt < ntl; lt += kBlock - kWave) {
+                    tkeyl[lt] = tkey[lt];
+                    tthrl[lt] = tsph[lt].w;
+                    tbestl[lt] = tbest[lt];
                     tflag[lt] = 0;
                 }
-                const unsigned long long k = tin ? kr : 0ull;
-                const bool top = k > lk;
-                lk2 = top ? lk : umax64(lk2, k);
-                lt_best = top ? (uint32_t)lt : lt_best;
-                lk = top ? k : lk;
             }
+            __syncthreads();
             if (clocks) {
                 const unsigned long long t = wall_clock64();
                 tl.sub[4] += t - t_mark;
                 tl.sub[5] -= t;  // the steps end at the phase mark below
             }
-            for (int s = 0; s < R; ++s) {
-                // arg max over the local tile keys (key and tile travel
-                // together; step 0's was taken with the copy)
-                if (clocks)
-                    tl.sub[9] -= wall_clock64();
-                if (s > 0) {
+            if (wave == 0 && more) {
+                for (int s = 1; s < R; ++s) {
+                    // local update with l_{s-1} (pruned against the local thresholds)
+                    for (int lt0 = 0; lt0 < ntl; lt0 += kWave) {
+                        const int lt = lt0 + lane;
+                        const int li = lt < ntl ? lt : 0;
+                        unsigned long long m =
+                            ballot64(!(sqdist(tsph[li].x, tsph[li].y, tsph[li].z, lx, ly, lz) >= tthrl[li])) &
+                            ballot64(lt < ntl);
+                        while (m) {
+                            const int t = lt0 + (__ffsll((long long)m) - 1);
+                            m &= m - 1;
+                            const uint32_t meta = tmeta[t];
+                            const uint32_t ls = meta & 0xffffu, cnt = meta >> 16;
+                            const bool valid = (uint32_t)lane < cnt;
+                            const uint32_t pp = ls + (valid ? lane : 0);
+                            // the private copy starts from the true state the
+                            // first time a step of this round touches the tile
+                            const float dpl = pdl[pp], dpt = pd[pp];
+                            float d = tflag[t] ? dpl : dpt;
+                            bool upd = false;
+                            if (valid) {
+                                const float dx = px[pp] - lx, dy = py[pp] - ly, dz = pz[pp] - lz;
+                                const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+                                const bool skip = use_skip && (xx >= d || yy >= d || zz >= d);
+                                const float s2 = xx + yy;
+                                float tt = s2 + zz;
+                                if (euclid && !skip && tt < d)
+                                    tt = sqrt_class_top(tt);
+                                upd = !skip && tt < d;
+                                d = upd ? tt : d;
+                                pdl[pp] = d;
+                            }
+                            if (lane == 0)
+                                tflag[t] = 1;
+                            if (__ballot(upd))
+                                tile_rekey<1>(lane, t, ls, cnt, d, po[pp], trad, tkeyl, tbestl, tthrl);
+                        }
+                    }
+                    // arg max over the private tile keys (key and tile travel together)
                     lk = 0;
                     lk2 = 0;
                     lt_best = 0;
@@ -443,91 +537,7 @@ __device__ bool sample_cloud(const RoundArgs &a, const CloudJob &job, int rank, 
                         lt_best = top ? (uint32_t)lt : lt_best;
                         lk = top ? k : lk;
                     }
-                }
-                const unsigned long long bk = wave_max_u64(lk);
-                const unsigned long long hit = bk != 0 ? ballot64(lk == bk) : 0ull;
-                if (bk == 0) {
-                    // a workgroup without points: bound 0, no candidates
-                    // (every point's key is above 0, so this is step 0)
-                    if (lane == 0)
-                        for (int w = 0; w < W; ++w)
-                            sh.my[w] = 0;
-                    if (clocks)
-                        tl.sub[9] += wall_clock64();
-                    break;
-                }
-                const uint32_t bt = (uint32_t)__builtin_amdgcn_readlane((int)lt_best, __ffsll((long long)hit) - 1);
-                const uint32_t p = tbestl[bt];
-                const float lx = px[p], ly = py[p], lz = pz[p];
-                // runner-up: the largest local key of any other point of this
-                // workgroup (other tiles, and the rest of the best tile); it
-                // bounds them if this candidate is not taken at its turn.  One
-                // reduction takes both parts.
-                unsigned long long ru;
-                {
-                    const uint32_t meta = tmeta[bt];
-                    const uint32_t ls = meta & 0xffffu, cnt = meta >> 16;
-                    const bool valid = (uint32_t)lane < cnt;
-                    const uint32_t pp = ls + (valid ? lane : 0);
-                    const float dpl = pdl[pp], dpt = pd[pp];
-                    const float dl = tflag[bt] ? dpl : dpt;
-                    const unsigned long long k = valid ? pack_key(dl, po[pp]) : 0ull;
-                    ru = wave_max_u64(umax64(lk == bk ? lk2 : lk, k == bk ? 0ull : k));
-                }
-                if (lane == 0) {
-                    sh.my[6 * s + 0] = __float_as_uint(lx);
-                    sh.my[6 * s + 1] = __float_as_uint(ly);
-                    sh.my[6 * s + 2] = __float_as_uint(lz);
-                    sh.my[6 * s + 3] = (uint32_t)(bk >> 32);  // local d2
-                    sh.my[6 * s + 4] = po[p];
-                    sh.my[6 * s + 5] = (uint32_t)(ru >> 32);  // runner-up d2
-                    if (s == R - 1) {
-                        // the bound: the runner-up, or l_R itself at distance 0
-                        const unsigned long long b = umax64(ru, pack_key(0.0f, po[p]));
-                        sh.my[6 * R] = (uint32_t)(b >> 32);
-                        sh.my[6 * R + 1] = (uint32_t)b;
-                    }
-                }
-                if (clocks)
-                    tl.sub[9] += wall_clock64();
-                if (s == R - 1)
-                    break;  // l_R is not applied to the private copy
-                // local update with l_s (pruned against the local thresholds)
-                for (int lt0 = 0; lt0 < ntl; lt0 += kWave) {
-                    const int lt = lt0 + lane;
-                    const int li = lt < ntl ? lt : 0;
-                    unsigned long long m =
-                        ballot64(!(sqdist(tsph[li].x, tsph[li].y, tsph[li].z, lx, ly, lz) >= tthrl[li])) &
-                        ballot64(lt < ntl);
-                    while (m) {
-                        const int t = lt0 + (__ffsll((long long)m) - 1);
-                        m &= m - 1;
-                        const uint32_t meta = tmeta[t];
-                        const uint32_t ls = meta & 0xffffu, cnt = meta >> 16;
-                        const bool valid = (uint32_t)lane < cnt;
-                        const uint32_t pp = ls + (valid ? lane : 0);
-                        // the private copy starts from the true state the
-                        // first time a step of this round touches the tile
-                        const float dpl = pdl[pp], dpt = pd[pp];
-                        float d = tflag[t] ? dpl : dpt;
-                        bool upd = false;
-                        if (valid) {
-                            const float dx = px[pp] - lx, dy = py[pp] - ly, dz = pz[pp] - lz;
-                            const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-                            const bool skip = use_skip && (xx >= d || yy >= d || zz >= d);
-                            const float s2 = xx + yy;
-                            float tt = s2 + zz;
-                            if (euclid && !skip && tt < d)
-                                tt = sqrt_class_top(tt);
-                            upd = !skip && tt < d;
-                            d = upd ? tt : d;
-                            pdl[pp] = d;
-                        }
-                        if (lane == 0)
-                            tflag[t] = 1;
-                        if (__ballot(upd))
-                            tile_rekey<1>(lane, t, ls, cnt, d, po[pp], trad, tkeyl, tbestl, tthrl);
-                    }
+                    select(s, false);
                 }
             }
         }
