@@ -140,8 +140,9 @@ typedef struct rfps_telemetry {
     /* finer clocks of workgroup 0 (multi-pick sampler, single cloud): the
      * merge's listing (key compaction and any cut of a long list), its
      * ranking pass, its certification walk and its hand-over of the picks;
-     * the lookahead's copy of the tile state and its steps; the exchange's
-     * polling and its forming of the candidate keys */
+     * the lookahead's first step (on the true tile state, while the other
+     * wavefronts copy it to the private state) and its later steps; the
+     * exchange's polling and its forming of the candidate keys */
     int64_t ticks_merge_list;
     int64_t ticks_merge_rank;
     int64_t ticks_merge_walk;
